@@ -1,0 +1,33 @@
+"""Plain FP64 CPU oracle for the cut-cell flux-stencil method of Devendran, Graves and
+Johansen, "A higher-order finite-volume discretization method for Poisson's equation
+in cut cell geometries" (arXiv:1411.4283).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or execute
+anything in this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP library;
+the only common dependency is the seeded input generator ``cutgeom``.
+
+The oracle follows the paper's definitions directly, face by face, in numpy FP64 (a
+LAPACK minimum-norm least-squares solve is the only library step of the stencil).
+Every function cites the passage it implements.
+"""
+
+from .stencils import (  # noqa: F401
+    Enumeration,
+    enumerate_geometry,
+    neighbours,
+    face_system,
+    face_stencil,
+    face_condition,
+    face_centre,
+    flux_vector,
+    recentre,
+    row_weights,
+    volumes_within,
+    build,
+    apply,
+    STATUS_OK,
+    STATUS_INSUFFICIENT_ROWS,
+    STATUS_RANK_DEFICIENT,
+    STATUS_NONFINITE,
+)
