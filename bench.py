@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the flux-stencil hot path on one MI355X.
+
+One step = the whole path over one batch of input already resident in HBM:
+  build (face enumeration, path-radius neighbour rows, binning by row count, row
+  assembly, weighted least-squares solve per face) followed by the operator apply
+  L(Phi) (face-flux gather and divergence).
+Workload: the 3D fourth-order case -- unit cube minus the sphere of radius 0.3 centred
+at (0.5, 0.5, 0.5) on a 64^3 grid, 35 monomials, path radius 3, Dirichlet boundaries,
+Phi ~ N(0, 1) (seed 2).  Inputs are synthetic: the moments come from host quadrature of
+the level set (cutgeom), done before the timed region.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cut-face stencils/s (3D, order 4, FP64) + L(phi) apply GB/s at 1e-11 rel err"
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector (= FP64 matrix) peak
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def householder_flops(N, M, T):
+    """Per-face flop count of a backward-stable weighted least-squares stencil solve
+    (LAPACK counts): Householder QR of the N x M weighted matrix, row assembly with T
+    binomial terms per row, the minimum-norm solve and the weighting."""
+    return (2 * N * M * M - 2.0 / 3.0 * M**3) + 2 * N * T + 2 * N * M + M * M + (4 * N * M - 2 * M * M) + N
+
+
+def workload(name):
+    import cutgeom as cg
+
+    if name == "c3":
+        return dict(shape=cg.ball_outside((0.5, 0.5, 0.5), 0.3), n=64, Q=4, R=3, seed=2,
+                    desc="3D order 4: 64^3 unit cube minus sphere r=0.3 at (0.5,0.5,0.5), path radius 3, "
+                         "35 monomials, Dirichlet, phi ~ N(0,1) seed 2")
+    if name == "c1":
+        return dict(shape=cg.ball_outside((0.5, 0.5), 0.25), n=32, Q=2, R=2, seed=2,
+                    desc="2D order 2: 32^2 unit square minus disk r=0.25, path radius 2, 6 monomials")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(g, R, sample, seed=7):
+    """The oracle (plain FP64 numpy, one thread) on a random sample of faces: build
+    (neighbours, rows, weights, stencil) plus each face's flux in the apply, and the
+    enumeration pro rata.  Returns faces/s."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        en = oracle.enumerate_geometry(g)
+        t_enum = time.perf_counter() - t0
+        faces = np.random.default_rng(seed).choice(en.n_face, min(sample, en.n_face), replace=False)
+        phi = np.random.default_rng(2).standard_normal(en.n_phi)
+        t0 = time.perf_counter()
+        for f in faces:
+            idx, s, st = oracle.face_stencil(g, en, int(f), R)
+            _ = float(np.dot(s, phi[idx]))
+        t_faces = time.perf_counter() - t0
+    t = t_faces + t_enum * len(faces) / en.n_face
+    return dict(value=len(faces) / t, unit="faces/s", cores=1, kind="oracle",
+                sample=f"{len(faces)} faces drawn uniformly (seed {seed}) of {en.n_face}; stencil build + "
+                       f"face flux per face, enumeration pro rata; {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design note, "
+              "not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import cutgeom as cg
+    import paper_1411_4283_amd as cc
+    from paper_1411_4283_amd import _lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workload(args.workload)
+    t0 = time.perf_counter()
+    g = cg.make_geometry(w["shape"], w["n"], w["Q"])
+    log(f"geometry {time.perf_counter() - t0:.2f} s")
+    dev = torch.device("cuda:0")
+    dg = cc.DeviceGeometry.from_host(g, dev)
+    b = cc.Builder(dg, w["R"])
+    s = b.query()
+    st = b.allocate()
+    phi = torch.from_numpy(np.random.default_rng(w["seed"]).standard_normal(s.n_phi)).to(dev)
+    lphi = torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=dev)
+    flux = torch.empty(max(s.n_face, 1), dtype=torch.float64, device=dev)
+    log(f"faces {s.n_face} nnz {s.nnz} phi {s.n_phi} max rows {s.max_rows}")
+
+    for _ in range(args.warmup):
+        b.build(out=st)
+        cc.apply(st, phi, lphi, flux)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    _lib.set_profiling(True)
+    solve_ms, apply_ms, phases = [], [], []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        b.build(out=st)
+        prof = _lib.last_profile()
+        solve_ms.append(prof["solve"])
+        phases.append(prof)
+        ev[k][0].record(stream)
+        cc.apply(st, phi, lphi, flux)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _lib.set_profiling(False)
+    apply_ms = [a.elapsed_time(z) for a, z in ev]
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    log(f"ms/step {ms_per_step:.3f}  solve {np.mean(solve_ms):.3f} ms  apply {np.mean(apply_ms) * 1e3:.1f} us")
+
+    rp = st.row_ptr.cpu().numpy()
+    N = np.diff(rp)
+    M = math.comb(w["Q"] + g.D, g.D)
+    T = math.comb(w["Q"] + 2 * g.D, 2 * g.D)
+    status = st.status.cpu().numpy()[: s.n_face]
+    ok = status == 0
+    flops = float(np.sum(householder_flops(N[ok].astype(np.float64), M, T)))
+    solve = float(np.mean(solve_ms))
+    achieved_tf = flops / (solve * 1e-3) / 1e12
+    apply_mean = float(np.mean(apply_ms))
+    bytes_alg = 12 * s.nnz + 8 * (s.n_face + 1) + 8 * s.n_phi + 16 * s.n_vol
+    apply_gbs = bytes_alg / (apply_mean * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": s.n_face / (ms_per_step * 1e-3),
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "grid": w["n"], "order": w["Q"], "path_radius": w["R"],
+                   "n_face": int(s.n_face), "nnz": int(s.nnz), "n_phi": int(s.n_phi), "n_vol": int(s.n_vol)},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_stencil (all row-count bins)", "kernel_ms": solve,
+                     "flops_per_launch": flops},
+        "roofline_apply": {"bound": "hbm", "achieved": apply_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": apply_gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "k_flux + k_divergence",
+                           "kernel_ms": apply_mean, "bytes_per_launch": bytes_alg},
+        "apply_gbps": apply_gbs,
+        "build_faces_per_s": s.n_face / (float(np.mean([sum(v for v in p.values() if v > 0) for p in phases])) * 1e-3),
+        "phases_ms": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, w["R"], args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

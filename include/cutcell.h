@@ -1,0 +1,182 @@
+/*
+ * cutcell.h -- C ABI of the MI355X (gfx950) flux-stencil library for the higher-order
+ * cut-cell finite-volume Poisson method of D. Devendran, D. T. Graves and H. Johansen,
+ * "A higher-order finite-volume discretization method for Poisson's equation in cut cell
+ * geometries" (arXiv:1411.4283).
+ *
+ * The library builds, for every face of a single-valued cut-cell grid, the weighted
+ * least-squares flux stencil  s = W (A^T W)^+ F  (Sec. 2.2.1, eq. 'stencil equation
+ * solution') and applies the flux-divergence operator L(Phi) those stencils define
+ * (Sec. 2.2, eq. 'laplacian over V'; Sec. 3.3).
+ *
+ * ---------------------------------------------------------------------------------------
+ * Conventions
+ *
+ *  Grid.  Cells [i h, (i+1) h] of the box [0, n_d h]^D, indexed linearly with x fastest:
+ *    c = i0 + n0*(i1 + n1*i2).  Grid faces of direction d form a lattice with n_d + 1
+ *    points along d (the other extents as for cells), indexed the same way; face j lies
+ *    on x_d = j_d h between cells j - e_d and j.
+ *  Monomials.  Multi-indices p with |p| <= Q in graded order: degree ascending; inside a
+ *    degree p_1 descending, then p_2 descending (the last exponent varies fastest).
+ *    M = C(Q+D, D) (6, 15 or 35), Mf = C(Q+D-1, D-1) transverse face monomials (in the
+ *    D-1 directions other than d, in increasing direction order), M1 = C(Q-1+D, D).
+ *  Moments (Sec. 2.1, eqs. 'volume moment', 'face moment', 'face moment with normal'),
+ *    scaled: with xi = (x - c)/h about the Cartesian centre c of the cell (or face),
+ *      vol_mom[c][p]      = int_V  xi^p dV / h^D        (vol_mom[c][0] = kappa)
+ *      face_mom[d][f][q]  = int_A  xi^q dA / h^(D-1)    (transverse q; [0] = alpha)
+ *      eb_mom[e][p]       = int_EB xi^p dA / h^(D-1)    about the cut cell's centre
+ *      eb_nmom[e][d][q]   = int_EB xi^q n_d dA / h^(D-1), |q| <= Q-1, n out of the fluid
+ *    A cell with kappa > 0 is a volume; kappa = 0 is covered.  A grid face with
+ *    alpha > 0 is a flux face.  Single-valued cells only (one volume and at most one
+ *    EB face per cell).
+ *  Phi (eq. 'def of phi vec').  [volumes | EB faces | box faces]: volumes by cell index,
+ *    EB faces in input order (eb_cell ascending), box faces (grid faces on the box
+ *    boundary with alpha > 0) by (direction d, side low=0/high=1, adjacent cell index).
+ *    In a batch, geometry g's block starts at phi_off[g] and the blocks follow in order.
+ *  Flux faces (CSR rows).  Per geometry: grid faces with alpha > 0 by (d, lattice index),
+ *    box faces included, then the EB faces in input order; geometries follow in order.
+ *    Reference normal +e_d for grid faces, out of the fluid for EB faces.
+ *  Neighbours (Sec. 2.4).  The volumes within path distance R_n (steps through grid
+ *    faces with alpha > 0) of the face's adjacent volumes, then every EB face and box
+ *    face those volumes touch; col[] lists their Phi indices in ascending order.
+ *  Centring (Sec. 2.4).  x0 = face centre for grid faces; for an EB face the centroid
+ *    of the cut volume.  Weights W_i = 1 if d_i < 1/2 else (2 d_i)^-5, d_i = |x_i - x0|/h,
+ *    x_i the Cartesian centre of the row's cell (volume and EB rows) or face (box rows).
+ *  Values.  val[] holds the physical stencil s = h^(D-2) W (A~^T W)^+ F~, so
+ *    flux_f = sum_j val[j] Phi[col[j]] approximates int_f grad(phi).n dA, and
+ *    L_v = (1/(kappa_v h^D)) sum_f sigma_vf flux_f with sigma = +1 when the face's
+ *    reference normal points out of v.
+ *
+ *  Memory.  Every array argument is DEVICE memory owned by the caller, except the
+ *    structs themselves and cutcell_sizes, which live on the host.  The library keeps no
+ *    state between calls and allocates no device memory: scratch comes from the caller's
+ *    workspace (size from cutcell_workspace_bytes).  Work is enqueued on `stream` (a
+ *    hipStream_t; 0 = the null stream).  cutcell_query and cutcell_build_stencils
+ *    synchronise `stream` before returning (they read counts back); cutcell_apply does not.
+ *
+ *  Errors.  Every entry point returns CUTCELL_OK (0), CUTCELL_W_FLAGGED_FACES (> 0:
+ *    success, some faces got a nonzero status) or a negative CUTCELL_E_* code; the
+ *    message of the last error on the calling thread is cutcell_last_error().  The
+ *    library never aborts.  A face whose system cannot be solved gets a status code and
+ *    val = 0 on its row.
+ * ---------------------------------------------------------------------------------------
+ */
+#ifndef CUTCELL_H
+#define CUTCELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CUTCELL_ABI_VERSION 1
+
+enum {
+  CUTCELL_OK = 0,
+  CUTCELL_W_FLAGGED_FACES = 1,
+  CUTCELL_E_INVALID_ARG = -1,  /* null pointer, bad size, inconsistent sizes          */
+  CUTCELL_E_UNSUPPORTED = -2,  /* D not in {2,3}, Q not in {2,4}, R_n out of [1, 4],
+                                  a face with more rows than the largest kernel bin   */
+  CUTCELL_E_WORKSPACE = -3,    /* workspace missing or smaller than required          */
+  CUTCELL_E_HIP = -4,          /* a HIP runtime call failed (message kept)            */
+  CUTCELL_E_CAPACITY = -5      /* output arrays smaller than the sizes require        */
+};
+
+/* Per-face status (Sec. 2.2.1 asks for "sufficiently many neighbors" and a full-rank
+ * system; a face that has neither gets val = 0 and one of these codes). */
+enum {
+  CUTCELL_STATUS_OK = 0,
+  CUTCELL_STATUS_INSUFFICIENT_ROWS = 1, /* fewer rows than monomials (N < M)            */
+  CUTCELL_STATUS_RANK_DEFICIENT = 2,    /* min L_kk <= 1e-7 max L_kk for the Cholesky
+                                           factor of the column-equilibrated W A       */
+  CUTCELL_STATUS_NONFINITE = 3          /* a non-finite moment or weight in the system  */
+};
+
+typedef void* cutcell_stream_t; /* hipStream_t */
+
+typedef struct {
+  int32_t dim;          /* D: 2 or 3                                                   */
+  int32_t n[3];         /* cells per direction (n[2] ignored when D = 2)               */
+  double h;             /* grid spacing                                                */
+  int32_t order;        /* Q: 2 or 4 (interpolant degree Q, P = Q + 1; Sec. 2.3)       */
+  int32_t path_radius;  /* R_n, 1..4 (the paper uses 2 for Q = 2 and 3 for Q = 4)      */
+} cutcell_opts;
+
+/* One geometry: device arrays in the layouts above. */
+typedef struct {
+  const double* vol_mom;     /* [ncell][M]                                             */
+  const double* face_mom[3]; /* [nface_d][Mf] for d < D                                */
+  int32_t n_eb;              /* number of EB faces                                     */
+  const int32_t* eb_cell;    /* [n_eb] strictly ascending cell indices                 */
+  const double* eb_mom;      /* [n_eb][M]                                              */
+  const double* eb_nmom;     /* [n_eb][D][M1]                                          */
+} cutcell_geom;
+
+/* Totals over the batch (host struct, filled by cutcell_query). */
+typedef struct {
+  int64_t n_vol, n_eb, n_box, n_phi, n_face, nnz;
+  int32_t max_rows;     /* largest row count N of any face                             */
+  int32_t n_geom;
+} cutcell_sizes;
+
+/* Build outputs: device arrays allocated by the caller with the sizes from
+ * cutcell_query (n_geom entries plus one for the offset arrays). */
+typedef struct {
+  int64_t* row_ptr;     /* [n_face + 1]                                                */
+  int32_t* col;         /* [nnz]   Phi indices (global over the batch), ascending per row */
+  double* val;          /* [nnz]   physical stencil values                             */
+  int8_t* status;       /* [n_face] CUTCELL_STATUS_*                                   */
+  int32_t* vol_face;    /* [n_vol][2D+1] flux faces of each volume: for d < D the low
+                           face (slot 2d) and high face (slot 2d+1), then the EB face;
+                           -1 where there is none                                       */
+  double* vol_scale;    /* [n_vol] 1 / (kappa_v h^D)                                    */
+  int64_t* phi_off;     /* [n_geom + 1] start of each geometry's Phi block              */
+  int64_t* vol_off;     /* [n_geom + 1] start of each geometry's volumes                */
+  int64_t* face_off;    /* [n_geom + 1] start of each geometry's flux faces             */
+} cutcell_stencils;
+
+/* Bytes of device workspace the calls below need for this grid and batch size. */
+size_t cutcell_workspace_bytes(const cutcell_opts* opts, int32_t n_geom);
+
+/* Enumerates volumes, boundary faces and flux faces (Sec. 2.1) and counts each face's
+ * neighbour rows (Sec. 2.4) for a batch of n_geom geometries that share `opts`; fills
+ * *sizes.  Synchronises `stream`. */
+int cutcell_query(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                  void* workspace, size_t workspace_bytes, cutcell_sizes* sizes,
+                  cutcell_stream_t stream);
+
+/* Builds every face's stencil s = W (A^T W)^+ F (Sec. 2.2.1 and Sec. 2.4) into *out,
+ * whose arrays must hold `sizes` (from cutcell_query on the same inputs).  Returns
+ * CUTCELL_W_FLAGGED_FACES when some face got a nonzero status.  Synchronises `stream`. */
+int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                           const cutcell_sizes* sizes, cutcell_stencils* out,
+                           void* workspace, size_t workspace_bytes, cutcell_stream_t stream);
+
+/* Applies the operator (Sec. 2.2, eq. 'laplacian over V'; Sec. 3.3):
+ *   flux[f] = sum_j val[j] phi[col[j]]   (output, [n_face]; also the pass's scratch)
+ *   lphi[v] = vol_scale[v] * sum over v's faces of sigma * flux
+ * phi: [n_phi], lphi: [n_vol].  Asynchronous on `stream`. */
+int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
+                  const double* phi, double* lphi, double* flux, cutcell_stream_t stream);
+
+/* Observability: when enabled (per calling thread), cutcell_build_stencils records HIP
+ * events on its stream between its phases, and cutcell_last_profile copies the last
+ * build's phase durations in milliseconds into ms[0 .. n-1]: enumeration, row counts and
+ * their scan, neighbour fill, binning, stencil solves, volume tables (-1 where a phase did
+ * not run).  Returns the number of phases (6), or CUTCELL_E_INVALID_ARG. */
+void cutcell_set_profiling(int enable);
+int cutcell_last_profile(double* ms, int32_t n);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* cutcell_last_error(void);
+
+/* CUTCELL_ABI_VERSION of the loaded library. */
+int cutcell_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTCELL_H */

@@ -1,0 +1,134 @@
+"""ctypes declarations of the C ABI in include/cutcell.h (argument marshalling only)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcutcell.so")
+
+P = ctypes.c_void_p
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("h", ctypes.c_double),
+        ("order", ctypes.c_int32),
+        ("path_radius", ctypes.c_int32),
+    ]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [
+        ("vol_mom", P),
+        ("face_mom", P * 3),
+        ("n_eb", ctypes.c_int32),
+        ("eb_cell", P),
+        ("eb_mom", P),
+        ("eb_nmom", P),
+    ]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [
+        ("n_vol", ctypes.c_int64),
+        ("n_eb", ctypes.c_int64),
+        ("n_box", ctypes.c_int64),
+        ("n_phi", ctypes.c_int64),
+        ("n_face", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("max_rows", ctypes.c_int32),
+        ("n_geom", ctypes.c_int32),
+    ]
+
+
+class StencilArrays(ctypes.Structure):
+    _fields_ = [
+        ("row_ptr", P),
+        ("col", P),
+        ("val", P),
+        ("status", P),
+        ("vol_face", P),
+        ("vol_scale", P),
+        ("phi_off", P),
+        ("vol_off", P),
+        ("face_off", P),
+    ]
+
+
+OK = 0
+W_FLAGGED_FACES = 1
+E_INVALID_ARG = -1
+E_UNSUPPORTED = -2
+E_WORKSPACE = -3
+E_HIP = -4
+E_CAPACITY = -5
+
+STATUS_OK = 0
+STATUS_INSUFFICIENT_ROWS = 1
+STATUS_RANK_DEFICIENT = 2
+STATUS_NONFINITE = 3
+
+# every function the header declares, with its signature
+SIGNATURES = {
+    "cutcell_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Opts), ctypes.c_int32]),
+    "cutcell_query": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts), P, ctypes.c_size_t,
+                                     ctypes.POINTER(Sizes), P]),
+    "cutcell_build_stencils": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts),
+                                              ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P,
+                                              ctypes.c_size_t, P]),
+    "cutcell_apply": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P, P, P, P]),
+    "cutcell_set_profiling": (None, [ctypes.c_int]),
+    "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    "cutcell_last_error": (ctypes.c_char_p, []),
+    "cutcell_abi_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+class CutcellError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed with code {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libcutcell.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(python -m paper_1411_4283_amd.build_lib)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def check(code: int, where: str, allow_flagged: bool = True) -> int:
+    if code == OK or (allow_flagged and code == W_FLAGGED_FACES):
+        return code
+    msg = load().cutcell_last_error().decode()
+    raise CutcellError(code, where, msg)
+
+
+PHASES = ("enumerate", "count", "fill", "bin", "solve", "tables")
+
+
+def set_profiling(enable: bool) -> None:
+    load().cutcell_set_profiling(1 if enable else 0)
+
+
+def last_profile() -> dict:
+    buf = (ctypes.c_double * len(PHASES))()
+    n = load().cutcell_last_profile(buf, len(PHASES))
+    return {PHASES[i]: buf[i] for i in range(min(n, len(PHASES)))}

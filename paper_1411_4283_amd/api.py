@@ -1,0 +1,185 @@
+"""Python binding of libcutcell (torch tensors for device memory and streams).
+
+Every step of the method runs in the HIP library; this module only allocates the
+caller-owned buffers the C ABI asks for and passes pointers.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from math import comb
+
+import torch
+
+from . import _lib
+from ._lib import Geom, Opts, Sizes, StencilArrays, check, load
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+@dataclass
+class DeviceGeometry:
+    """One geometry's moments on the device, in the layouts of include/cutcell.h."""
+
+    dim: int
+    n: tuple
+    h: float
+    order: int
+    vol_mom: torch.Tensor           # [ncell, M] float64
+    face_mom: list                  # dim tensors [nface_d, Mf] float64
+    eb_cell: torch.Tensor           # [n_eb] int32, ascending
+    eb_mom: torch.Tensor            # [n_eb, M] float64
+    eb_nmom: torch.Tensor           # [n_eb, dim, M1] float64
+
+    @staticmethod
+    def from_host(g, device="cuda") -> "DeviceGeometry":
+        """From any object with the host arrays (D, n, h, Q, vol_mom, face_mom, eb_cell,
+        eb_mom, eb_nmom), e.g. the input generator's geometry."""
+
+        def t(a, dt):
+            return torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+
+        return DeviceGeometry(
+            dim=int(g.D), n=tuple(int(v) for v in g.n), h=float(g.h), order=int(g.Q),
+            vol_mom=t(g.vol_mom, torch.float64), face_mom=[t(f, torch.float64) for f in g.face_mom],
+            eb_cell=t(g.eb_cell, torch.int32), eb_mom=t(g.eb_mom, torch.float64),
+            eb_nmom=t(g.eb_nmom, torch.float64),
+        )
+
+    def struct(self) -> Geom:
+        s = Geom()
+        s.vol_mom = _ptr(self.vol_mom)
+        for d in range(3):
+            s.face_mom[d] = _ptr(self.face_mom[d]) if d < self.dim else None
+        s.n_eb = int(self.eb_cell.numel())
+        s.eb_cell = _ptr(self.eb_cell)
+        s.eb_mom = _ptr(self.eb_mom)
+        s.eb_nmom = _ptr(self.eb_nmom)
+        return s
+
+
+def make_opts(dim: int, n, h: float, order: int, path_radius: int) -> Opts:
+    o = Opts()
+    o.dim = dim
+    nn = list(n) + [1] * (3 - len(n))
+    for d in range(3):
+        o.n[d] = int(nn[d])
+    o.h = float(h)
+    o.order = int(order)
+    o.path_radius = int(path_radius)
+    return o
+
+
+@dataclass
+class Stencils:
+    """Build outputs (device tensors) and their sizes."""
+
+    dim: int
+    sizes: Sizes
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    status: torch.Tensor
+    vol_face: torch.Tensor
+    vol_scale: torch.Tensor
+    phi_off: torch.Tensor
+    vol_off: torch.Tensor
+    face_off: torch.Tensor
+    code: int = 0
+    _keep: list = field(default_factory=list, repr=False)
+
+    def struct(self) -> StencilArrays:
+        s = StencilArrays()
+        for name in ("row_ptr", "col", "val", "status", "vol_face", "vol_scale", "phi_off", "vol_off", "face_off"):
+            setattr(s, name, _ptr(getattr(self, name)))
+        return s
+
+
+class Builder:
+    """Holds the workspace and the ctypes structs of one batch of geometries sharing a
+    grid, order and path radius, so repeated builds allocate nothing new."""
+
+    def __init__(self, geoms, path_radius: int, device="cuda"):
+        geoms = list(geoms) if isinstance(geoms, (list, tuple)) else [geoms]
+        g0 = geoms[0]
+        for g in geoms:
+            assert (g.dim, g.n, g.h, g.order) == (g0.dim, g0.n, g0.h, g0.order), "a batch shares its grid"
+        self.geoms = geoms
+        self.dim = g0.dim
+        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius)
+        self.garr = (Geom * len(geoms))(*[g.struct() for g in geoms])
+        lib = load()
+        nbytes = lib.cutcell_workspace_bytes(ctypes.byref(self.opts), len(geoms))
+        if nbytes == 0:
+            raise ValueError("unsupported options")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.device = device
+        self.sizes = None
+
+    def query(self, stream=None) -> Sizes:
+        sizes = Sizes()
+        rc = load().cutcell_query(self.garr, len(self.geoms), ctypes.byref(self.opts), _ptr(self.workspace),
+                                  self.workspace.numel(), ctypes.byref(sizes), _stream(stream))
+        check(rc, "cutcell_query")
+        self.sizes = sizes
+        return sizes
+
+    def allocate(self) -> Stencils:
+        s = self.sizes if self.sizes is not None else self.query()
+        dev = self.device
+        G = len(self.geoms)
+        i64 = dict(dtype=torch.int64, device=dev)
+        return Stencils(
+            dim=self.dim, sizes=s,
+            row_ptr=torch.empty(s.n_face + 1, **i64),
+            col=torch.empty(max(s.nnz, 1), dtype=torch.int32, device=dev),
+            val=torch.empty(max(s.nnz, 1), dtype=torch.float64, device=dev),
+            status=torch.empty(max(s.n_face, 1), dtype=torch.int8, device=dev),
+            vol_face=torch.empty(max(s.n_vol, 1) * (2 * self.dim + 1), dtype=torch.int32, device=dev),
+            vol_scale=torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=dev),
+            phi_off=torch.empty(G + 1, **i64), vol_off=torch.empty(G + 1, **i64), face_off=torch.empty(G + 1, **i64),
+        )
+
+    def build(self, out: Stencils | None = None, stream=None) -> Stencils:
+        if self.sizes is None:
+            self.query(stream)
+        out = self.allocate() if out is None else out
+        arr = out.struct()
+        rc = load().cutcell_build_stencils(self.garr, len(self.geoms), ctypes.byref(self.opts),
+                                           ctypes.byref(self.sizes), ctypes.byref(arr), _ptr(self.workspace),
+                                           self.workspace.numel(), _stream(stream))
+        out.code = check(rc, "cutcell_build_stencils")
+        return out
+
+
+def build_stencils(geoms, path_radius: int, stream=None) -> Stencils:
+    """Flux stencils of every face of one geometry (or a batch sharing a grid)."""
+    return Builder(geoms, path_radius).build(stream=stream)
+
+
+def apply(st: Stencils, phi: torch.Tensor, lphi: torch.Tensor | None = None, flux: torch.Tensor | None = None,
+          stream=None):
+    """L(Phi) = divergence of the face fluxes s_f^T Phi; returns (lphi, flux)."""
+    s = st.sizes
+    assert phi.dtype == torch.float64 and phi.is_contiguous() and phi.numel() == s.n_phi
+    if lphi is None:
+        lphi = torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=phi.device)
+    if flux is None:
+        flux = torch.empty(max(s.n_face, 1), dtype=torch.float64, device=phi.device)
+    arr = st.struct()
+    rc = load().cutcell_apply(ctypes.byref(s), st.dim, ctypes.byref(arr), _ptr(phi), _ptr(lphi), _ptr(flux),
+                              _stream(stream))
+    check(rc, "cutcell_apply", allow_flagged=False)
+    return lphi[: s.n_vol], flux[: s.n_face]
+
+
+def n_monomials(dim: int, order: int) -> int:
+    return comb(order + dim, dim)

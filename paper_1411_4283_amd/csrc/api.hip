@@ -1,0 +1,321 @@
+// Host entry points of the C ABI declared in include/cutcell.h.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "scan.hpp"
+
+namespace cutcell {
+
+static thread_local std::string g_last_error;
+
+// ---- optional per-phase timing of cutcell_build_stencils (hipEvents on its stream) ------
+constexpr int kPhases = 6;   // enumerate, count+scan, fill, bin, solve, tables
+static thread_local bool g_profiling = false;
+static thread_local double g_phase_ms[kPhases] = {-1, -1, -1, -1, -1, -1};
+
+struct PhaseTimer {
+  hipEvent_t ev[kPhases + 1];
+  int n = 0;
+  bool on;
+  hipStream_t st;
+  PhaseTimer(hipStream_t s) : on(g_profiling), st(s) {
+    if (!on) return;
+    for (int i = 0; i <= kPhases; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) on = false;
+  }
+  void mark() {
+    if (on && n <= kPhases) (void)hipEventRecord(ev[n++], st);
+  }
+  void finish() {
+    if (!on) return;
+    (void)hipEventSynchronize(ev[n - 1]);
+    for (int i = 0; i < kPhases; ++i) {
+      float ms = 0.f;
+      g_phase_ms[i] = (i + 1 < n && hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) ? ms : -1.0;
+    }
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    for (int i = 0; i <= kPhases; ++i) (void)hipEventDestroy(ev[i]);
+  }
+};
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
+  Work t{};
+  t.dims = make_dims(o);
+  t.G = G;
+  const GridDims& g = t.dims;
+  t.L = g.ncell + g.nboxslot + g.NF;
+  t.maxface = g.NF + g.ncell;
+  const long long tilesL = scan_tiles(t.L);
+  const long long totface = (long long)G * t.maxface;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  t.flags = (int32_t*)take(sizeof(int32_t) * G * t.L);
+  t.excl = (int32_t*)take(sizeof(int32_t) * G * t.L);
+  t.seg_total = (int32_t*)take(sizeof(int32_t) * G);
+  t.scan_tmp = (int32_t*)take(sizeof(int32_t) * G * tilesL);
+  t.vol_id = (int32_t*)take(sizeof(int32_t) * G * g.ncell);
+  t.eb_id = (int32_t*)take(sizeof(int32_t) * G * g.ncell);
+  t.face_id = (int32_t*)take(sizeof(int32_t) * G * g.NF);
+  t.box_id = (int32_t*)take(sizeof(int32_t) * G * g.NF);
+  t.box_lf = (int32_t*)take(sizeof(int32_t) * G * std::max<long long>(g.nboxslot, 1));
+  t.vol_cell = (int32_t*)take(sizeof(int32_t) * G * g.ncell);
+  t.counts = (int64_t*)take(sizeof(int64_t) * 4 * G);
+  t.offs = (int64_t*)take(sizeof(int64_t) * 3 * (G + 1));
+  t.fcode = (int32_t*)take(sizeof(int32_t) * totface);
+  t.fref = (int32_t*)take(sizeof(int32_t) * totface);
+  t.nrows = (int32_t*)take(sizeof(int32_t) * totface);
+  t.scan64 = (int64_t*)take(sizeof(int64_t) * (scan_tiles(totface) + 1));
+  t.rp_tmp = (int64_t*)take(sizeof(int64_t) * (totface + 1));
+  t.perm = (int32_t*)take(sizeof(int32_t) * totface);
+  t.bins = (int32_t*)take(sizeof(int32_t) * kBinWords);
+  t.flagged = (int32_t*)take(sizeof(int32_t) * 2);
+  t.geoms = (GeomPtrs*)take(sizeof(GeomPtrs) * G);
+  t.bytes = off;
+  if (w) *w = t;
+  return off;
+}
+
+static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
+  if (!o) return fail(CUTCELL_E_INVALID_ARG, "opts is NULL");
+  if (o->dim != 2 && o->dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (o->order != 2 && o->order != 4) return fail(CUTCELL_E_UNSUPPORTED, "order must be 2 or 4");
+  if (o->path_radius < 1 || o->path_radius > 4) return fail(CUTCELL_E_UNSUPPORTED, "path_radius must be in [1, 4]");
+  if (!(o->h > 0)) return fail(CUTCELL_E_INVALID_ARG, "h must be positive");
+  for (int d = 0; d < o->dim; ++d)
+    if (o->n[d] < 1 || o->n[d] > (1 << 14)) return fail(CUTCELL_E_INVALID_ARG, "n[d] out of range");
+  long long ncell = 1;
+  for (int d = 0; d < o->dim; ++d) ncell *= o->n[d];
+  if (G < 1 || G > (1 << 20)) return fail(CUTCELL_E_INVALID_ARG, "n_geom out of range");
+  if ((long long)G * (ncell * 4 + 64) > (1LL << 31)) return fail(CUTCELL_E_UNSUPPORTED, "batch too large for 32-bit indices");
+  if (!geoms) return fail(CUTCELL_E_INVALID_ARG, "geoms is NULL");
+  for (int i = 0; i < G; ++i) {
+    const cutcell_geom& g = geoms[i];
+    if (!g.vol_mom) return fail(CUTCELL_E_INVALID_ARG, "vol_mom is NULL");
+    for (int d = 0; d < o->dim; ++d)
+      if (!g.face_mom[d]) return fail(CUTCELL_E_INVALID_ARG, "face_mom[d] is NULL");
+    if (g.n_eb < 0 || g.n_eb > ncell) return fail(CUTCELL_E_INVALID_ARG, "n_eb out of range");
+    if (g.n_eb > 0 && (!g.eb_cell || !g.eb_mom || !g.eb_nmom)) return fail(CUTCELL_E_INVALID_ARG, "EB arrays are NULL");
+  }
+  return CUTCELL_OK;
+}
+
+// EB cells must be strictly ascending, inside the grid and in volumes (checked on the
+// device before anything indexes with them)
+__global__ void k_check_eb(int G, long long ncell, int M, const GeomPtrs* __restrict__ geoms, int32_t* bad) {
+  const int gi = blockIdx.y;
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const GeomPtrs gp = geoms[gi];
+  if (e >= gp.n_eb) return;
+  const int32_t c = gp.eb_cell[e];
+  bool ok = c >= 0 && c < ncell;
+  if (ok && e > 0) ok = gp.eb_cell[e - 1] < c;
+  if (ok) ok = gp.vol_mom[(long long)c * M] > 0.0;
+  if (!ok) atomicOr(bad, 1);
+}
+
+struct Prepared {
+  Work w;
+  std::vector<int64_t> counts, offs;
+  int64_t n_vol = 0, n_eb = 0, n_box = 0, n_phi = 0, n_face = 0;
+};
+
+static int prepare(const cutcell_geom* geoms, int G, const cutcell_opts* o, void* ws, size_t ws_bytes, hipStream_t st,
+                   Prepared* P) {
+  int rc = validate(geoms, G, o);
+  if (rc) return rc;
+  const size_t need = layout_work(*o, G, nullptr, nullptr);
+  if (!ws || ws_bytes < need)
+    return fail(CUTCELL_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  layout_work(*o, G, (char*)ws, &P->w);
+  const Work& w = P->w;
+  std::vector<GeomPtrs> gp(G);
+  for (int i = 0; i < G; ++i) {
+    gp[i].vol_mom = geoms[i].vol_mom;
+    for (int d = 0; d < 3; ++d) gp[i].face_mom[d] = (d < o->dim) ? geoms[i].face_mom[d] : nullptr;
+    gp[i].eb_cell = geoms[i].eb_cell;
+    gp[i].eb_mom = geoms[i].eb_mom;
+    gp[i].eb_nmom = geoms[i].eb_nmom;
+    gp[i].n_eb = geoms[i].n_eb;
+  }
+  CC_HIP(hipMemcpyAsync(w.geoms, gp.data(), sizeof(GeomPtrs) * G, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.flagged, 2LL, 0);
+  const int M = binom(o->order + o->dim, o->dim);
+  int maxeb = 0;
+  for (int i = 0; i < G; ++i) maxeb = std::max(maxeb, geoms[i].n_eb);
+  if (maxeb > 0)
+    hipLaunchKernelGGL(k_check_eb, dim3((unsigned)((maxeb + 255) / 256), G), dim3(256), 0, st, G, w.dims.ncell, M,
+                       w.geoms, w.flagged + 1);
+  rc = enumerate_batch(w, *o, st);
+  if (rc) return rc;
+  P->counts.assign(4 * G, 0);
+  P->offs.assign(3 * (G + 1), 0);
+  int32_t bad = 0;
+  CC_HIP(hipMemcpyAsync(P->counts.data(), w.counts, sizeof(int64_t) * 4 * G, hipMemcpyDeviceToHost, st));
+  CC_HIP(hipMemcpyAsync(P->offs.data(), w.offs, sizeof(int64_t) * 3 * (G + 1), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipMemcpyAsync(&bad, w.flagged + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (bad) return fail(CUTCELL_E_INVALID_ARG, "eb_cell must be strictly ascending cells with kappa > 0");
+  for (int i = 0; i < G; ++i) {
+    P->n_vol += P->counts[4 * i + 0];
+    P->n_eb += P->counts[4 * i + 1];
+    P->n_box += P->counts[4 * i + 2];
+  }
+  P->n_phi = P->offs[G];
+  P->n_face = P->offs[2 * (G + 1) + G];
+  if (P->n_phi >= (1LL << 31)) return fail(CUTCELL_E_UNSUPPORTED, "more than 2^31 Phi rows");
+  return CUTCELL_OK;
+}
+
+// counts rows per face, scans them into row_ptr (int64); returns nnz and max rows
+static int count_rows(const Prepared& P, const cutcell_opts* o, int64_t* row_ptr, int64_t* nnz, int32_t* maxrows,
+                      hipStream_t st) {
+  const Work& w = P.w;
+  int rc = neighbour_rows(w, *o, P.n_face, nullptr, nullptr, false, st);
+  if (rc) return rc;
+  int64_t total = 0;
+  if (P.n_face > 0) {
+    rc = exclusive_scan<int32_t, int64_t>(w.nrows, P.n_face, P.n_face, 1, row_ptr, P.n_face, row_ptr ? row_ptr + P.n_face : nullptr,
+                                          w.scan64, st);
+    if (rc) return rc;
+  }
+  int32_t mr = 0;
+  CC_HIP(hipMemcpyAsync(&mr, w.bins + 2 * kNBuckets, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (row_ptr && P.n_face > 0)
+    CC_HIP(hipMemcpyAsync(&total, row_ptr + P.n_face, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  *nnz = total;
+  *maxrows = mr;
+  return CUTCELL_OK;
+}
+
+}  // namespace cutcell
+
+using namespace cutcell;
+
+extern "C" {
+
+size_t cutcell_workspace_bytes(const cutcell_opts* opts, int32_t n_geom) {
+  if (!opts || n_geom < 1 || (opts->dim != 2 && opts->dim != 3)) return 0;
+  return layout_work(*opts, n_geom, nullptr, nullptr);
+}
+
+int cutcell_query(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts, void* workspace,
+                  size_t workspace_bytes, cutcell_sizes* sizes, cutcell_stream_t stream) {
+  if (!sizes) return fail(CUTCELL_E_INVALID_ARG, "sizes is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  Prepared P;
+  int rc = prepare(geoms, n_geom, opts, workspace, workspace_bytes, st, &P);
+  if (rc) return rc;
+  int64_t nnz = 0;
+  int32_t mr = 0;
+  rc = count_rows(P, opts, P.w.rp_tmp, &nnz, &mr, st);
+  if (rc) return rc;
+  sizes->n_vol = P.n_vol;
+  sizes->n_eb = P.n_eb;
+  sizes->n_box = P.n_box;
+  sizes->n_phi = P.n_phi;
+  sizes->n_face = P.n_face;
+  sizes->nnz = nnz;
+  sizes->max_rows = mr;
+  sizes->n_geom = n_geom;
+  if (mr > kMaxRows)
+    return fail(CUTCELL_E_UNSUPPORTED, "a face has " + std::to_string(mr) + " rows; at most " +
+                                           std::to_string(kMaxRows) + " are supported");
+  return CUTCELL_OK;
+}
+
+int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                           const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
+                           cutcell_stream_t stream) {
+  if (!sizes || !out) return fail(CUTCELL_E_INVALID_ARG, "sizes/out is NULL");
+  if (!out->row_ptr || !out->col || !out->val || !out->status || !out->vol_face || !out->vol_scale ||
+      !out->phi_off || !out->vol_off || !out->face_off)
+    return fail(CUTCELL_E_INVALID_ARG, "an output array is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  PhaseTimer timer(st);
+  timer.mark();
+  Prepared P;
+  int rc = prepare(geoms, n_geom, opts, workspace, workspace_bytes, st, &P);
+  if (rc) return rc;
+  timer.mark();
+  if (sizes->n_geom != n_geom || sizes->n_face != P.n_face || sizes->n_vol != P.n_vol || sizes->n_phi != P.n_phi)
+    return fail(CUTCELL_E_CAPACITY, "sizes do not match these inputs (call cutcell_query first)");
+  const Work& w = P.w;
+  int64_t nnz = 0;
+  int32_t mr = 0;
+  rc = count_rows(P, opts, out->row_ptr, &nnz, &mr, st);
+  if (rc) return rc;
+  timer.mark();
+  if (nnz != sizes->nnz) return fail(CUTCELL_E_CAPACITY, "nnz differs from sizes->nnz");
+  if (mr > kMaxRows)
+    return fail(CUTCELL_E_UNSUPPORTED, "a face has " + std::to_string(mr) + " rows; at most " +
+                                           std::to_string(kMaxRows) + " are supported");
+  rc = neighbour_rows(w, *opts, P.n_face, out->row_ptr, out->col, true, st);
+  if (rc) return rc;
+  timer.mark();
+  const int M = binom(opts->order + opts->dim, opts->dim);
+  rc = bin_faces(w, P.n_face, M, st);
+  if (rc) return rc;
+  timer.mark();
+  int32_t bc[kBinWords];
+  CC_HIP(hipMemcpyAsync(bc, w.bins, sizeof(bc), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  rc = solve_stencils(w, *opts, bc, P.n_face, out->row_ptr, out->col, out->val, out->status, st);
+  if (rc) return rc;
+  timer.mark();
+  rc = volume_tables(w, *opts, P.n_vol, out->vol_face, out->vol_scale, st);
+  if (rc) return rc;
+  timer.mark();
+  const size_t ob = sizeof(int64_t) * (n_geom + 1);
+  CC_HIP(hipMemcpyAsync(out->phi_off, w.offs, ob, hipMemcpyDeviceToDevice, st));
+  CC_HIP(hipMemcpyAsync(out->vol_off, w.offs + (n_geom + 1), ob, hipMemcpyDeviceToDevice, st));
+  CC_HIP(hipMemcpyAsync(out->face_off, w.offs + 2 * (n_geom + 1), ob, hipMemcpyDeviceToDevice, st));
+  int32_t flagged = 0;
+  CC_HIP(hipMemcpyAsync(&flagged, w.flagged, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  CC_HIP(hipGetLastError());
+  timer.finish();
+  return flagged ? CUTCELL_W_FLAGGED_FACES : CUTCELL_OK;
+}
+
+void cutcell_set_profiling(int enable) { g_profiling = enable != 0; }
+
+int cutcell_last_profile(double* ms, int32_t n) {
+  if (!ms || n < 0) return fail(CUTCELL_E_INVALID_ARG, "ms is NULL");
+  for (int i = 0; i < n && i < kPhases; ++i) ms[i] = g_phase_ms[i];
+  return kPhases;
+}
+
+int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const double* phi,
+                  double* lphi, double* flux, cutcell_stream_t stream) {
+  if (!sizes || !st_ || !phi || !lphi || !flux) return fail(CUTCELL_E_INVALID_ARG, "NULL argument (flux is required)");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (!st_->row_ptr || !st_->col || !st_->val || !st_->vol_face || !st_->vol_scale)
+    return fail(CUTCELL_E_INVALID_ARG, "stencil arrays are NULL");
+  return apply_operator(dim, sizes->n_face, sizes->n_vol, st_->row_ptr, st_->col, st_->val, st_->vol_face,
+                        st_->vol_scale, phi, lphi, flux, nullptr, (hipStream_t)stream);
+}
+
+const char* cutcell_last_error(void) { return g_last_error.c_str(); }
+
+int cutcell_abi_version(void) { return CUTCELL_ABI_VERSION; }
+
+}  // extern "C"

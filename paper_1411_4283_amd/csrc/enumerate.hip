@@ -1,0 +1,473 @@
+// Enumeration of volumes, boundary faces and flux faces (Sec. 2.1), path-radius
+// neighbour rows (Sec. 2.4) and row-count binning.
+#include "kernels.hpp"
+#include "scan.hpp"
+
+namespace cutcell {
+
+__global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// lattice face lf (in the concatenated lattice) -> direction and coordinates
+__device__ __forceinline__ int lattice_dir(const GridDims& g, long long lf) {
+  return (lf >= g.foff[1]) + (lf >= g.foff[2]);
+}
+
+__device__ __forceinline__ void lattice_coords(const GridDims& g, int d, long long lf, int* j) {
+  long long loc = lf - g.foff[d];
+  int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
+  j[0] = (int)(loc % m0);
+  j[1] = (int)((loc / m0) % m1);
+  j[2] = (int)(loc / ((long long)m0 * m1));
+}
+
+__device__ __forceinline__ long long lattice_index(const GridDims& g, int d, const int* j) {
+  int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
+  return g.foff[d] + j[0] + (long long)m0 * (j[1] + (long long)m1 * j[2]);
+}
+
+__device__ __forceinline__ long long cell_index(const GridDims& g, const int* i) {
+  return i[0] + (long long)g.n[0] * (i[1] + (long long)g.n[1] * i[2]);
+}
+
+// box slot s (cells next to the box boundary, grouped by (d, side), ascending cell index
+// inside a group) -> direction, side and the box face's lattice index
+__device__ __forceinline__ long long box_slot_face(const GridDims& g, long long s, int* dd, int* side) {
+  int k = 0;
+  while (k < 5 && s >= g.boxoff[k + 1]) ++k;
+  const int d = k / 2, sd = k % 2;
+  long long t = s - g.boxoff[k];
+  int a = (d == 0) ? 1 : 0;           // the two other directions, ascending
+  int b = (d == 2) ? 1 : 2;
+  int i[3] = {0, 0, 0};
+  i[a] = (int)(t % g.n[a]);
+  i[b] = (int)(t / g.n[a]);
+  i[d] = sd ? g.n[d] : 0;             // lattice coordinate of the boundary face
+  *dd = d;
+  *side = sd;
+  return lattice_index(g, d, i);
+}
+
+__global__ void k_enum_flags(GridDims g, int M, int Mf, const GeomPtrs* __restrict__ geoms, int32_t* flags,
+                             long long L) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= L) return;
+  const int gi = blockIdx.y;
+  const GeomPtrs gp = geoms[gi];
+  int32_t f = 0;
+  if (i < g.ncell) {
+    f = gp.vol_mom[i * M] > 0.0;
+  } else if (i < g.ncell + g.nboxslot) {
+    int d, side;
+    long long lf = box_slot_face(g, i - g.ncell, &d, &side);
+    f = gp.face_mom[d][(lf - g.foff[d]) * Mf] > 0.0;
+  } else {
+    long long lf = i - g.ncell - g.nboxslot;
+    int d = lattice_dir(g, lf);
+    f = gp.face_mom[d][(lf - g.foff[d]) * Mf] > 0.0;
+  }
+  flags[gi * L + i] = f;
+}
+
+__global__ void k_enum_counts(GridDims g, int G, long long L, const int32_t* __restrict__ excl,
+                              const int32_t* __restrict__ seg_total, const GeomPtrs* __restrict__ geoms,
+                              int64_t* counts, int64_t* offs) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t* phi_off = offs;
+  int64_t* vol_off = offs + (G + 1);
+  int64_t* face_off = offs + 2 * (G + 1);
+  phi_off[0] = vol_off[0] = face_off[0] = 0;
+  for (int gi = 0; gi < G; ++gi) {
+    const int32_t* e = excl + gi * L;
+    int64_t n_vol = e[g.ncell];
+    int64_t n_box = (int64_t)e[g.ncell + g.nboxslot] - e[g.ncell];
+    int64_t n_gface = (int64_t)seg_total[gi] - e[g.ncell + g.nboxslot];
+    int64_t n_eb = geoms[gi].n_eb;
+    counts[4 * gi + 0] = n_vol;
+    counts[4 * gi + 1] = n_eb;
+    counts[4 * gi + 2] = n_box;
+    counts[4 * gi + 3] = n_gface;
+    phi_off[gi + 1] = phi_off[gi] + n_vol + n_eb + n_box;
+    vol_off[gi + 1] = vol_off[gi] + n_vol;
+    face_off[gi + 1] = face_off[gi] + n_gface + n_eb;
+  }
+}
+
+__global__ void k_enum_maps(GridDims g, int G, long long L, long long maxface, const int32_t* __restrict__ flags,
+                            const int32_t* __restrict__ excl, const int64_t* __restrict__ offs, int32_t* vol_id,
+                            int32_t* vol_cell, int32_t* box_id, int32_t* box_lf, int32_t* face_id, int32_t* fcode,
+                            int32_t* fref) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= L) return;
+  const int gi = blockIdx.y;
+  const int32_t f = flags[gi * L + i];
+  const int32_t e = excl[gi * L + i];
+  if (i < g.ncell) {
+    vol_id[gi * g.ncell + i] = f ? e : -1;
+    if (f) vol_cell[gi * g.ncell + e] = (int32_t)i;
+  } else if (i < g.ncell + g.nboxslot) {
+    if (!f) return;
+    int d, side;
+    long long lf = box_slot_face(g, i - g.ncell, &d, &side);
+    int32_t b = e - excl[gi * L + g.ncell];
+    box_id[gi * g.NF + lf] = b;
+    box_lf[gi * g.nboxslot + b] = (int32_t)lf;
+  } else {
+    long long lf = i - g.ncell - g.nboxslot;
+    int32_t loc = f ? e - excl[gi * L + g.ncell + g.nboxslot] : -1;
+    face_id[gi * g.NF + lf] = loc;
+    if (f) {
+      long long F = offs[2 * (G + 1) + gi] + loc;
+      fcode[F] = face_code(gi, 0, lattice_dir(g, lf));
+      fref[F] = (int32_t)lf;
+    }
+  }
+}
+
+__global__ void k_enum_eb(GridDims g, int G, const GeomPtrs* __restrict__ geoms, const int64_t* __restrict__ counts,
+                          const int64_t* __restrict__ offs, int32_t* eb_id, int32_t* fcode, int32_t* fref) {
+  const int gi = blockIdx.y;
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const GeomPtrs gp = geoms[gi];
+  if (e >= gp.n_eb) return;
+  int32_t c = gp.eb_cell[e];
+  if (c < 0 || c >= g.ncell) return;   // rejected by the argument check; never index with it
+  eb_id[gi * g.ncell + c] = (int32_t)e;
+  long long F = offs[2 * (G + 1) + gi] + counts[4 * gi + 3] + e;
+  fcode[F] = face_code(gi, 1, 0);
+  fref[F] = (int32_t)e;
+}
+
+int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st) {
+  const GridDims& g = w.dims;
+  const int D = o.dim, Q = o.order;
+  const int M = binom(Q + D, D), Mf = binom(Q + D - 1, D - 1);
+  const int T = 256;
+  hipLaunchKernelGGL(k_enum_flags, dim3(blocks_for(w.L, T), w.G), dim3(T), 0, st, g, M, Mf, w.geoms, w.flags, w.L);
+  int rc = exclusive_scan<int32_t, int32_t>(w.flags, w.L, w.L, w.G, w.excl, w.L, w.seg_total, w.scan_tmp, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_enum_counts, dim3(1), dim3(64), 0, st, g, w.G, w.L, w.excl, w.seg_total, w.geoms, w.counts,
+                     w.offs);
+  const long long nmap = (long long)w.G * g.NF;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nmap, T)), dim3(T), 0, st, w.box_id, nmap, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for((long long)w.G * g.ncell, T)), dim3(T), 0, st, w.eb_id,
+                     (long long)w.G * g.ncell, -1);
+  hipLaunchKernelGGL(k_enum_maps, dim3(blocks_for(w.L, T), w.G), dim3(T), 0, st, g, w.G, w.L, w.maxface, w.flags,
+                     w.excl, w.offs, w.vol_id, w.vol_cell, w.box_id, w.box_lf, w.face_id, w.fcode, w.fref);
+  hipLaunchKernelGGL(k_enum_eb, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, w.G, w.geoms, w.counts, w.offs,
+                     w.eb_id, w.fcode, w.fref);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// neighbours: breadth-first search by path distance inside a window around the face
+
+template <int D, int R>
+struct Win {
+  static constexpr int EN = 2 * R + 2;                       // extent along the face normal
+  static constexpr int ET = 2 * R + 1;                       // transverse extent
+  static constexpr int NW = EN * (D >= 2 ? ET : 1) * (D >= 3 ? ET : 1);
+  static constexpr int K = (NW + 63) / 64;                   // window cells per lane
+};
+
+template <int D, int R, bool FILL>
+__global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long n_face,
+                                                   const int32_t* __restrict__ fcode, const int32_t* __restrict__ fref,
+                                                   const GeomPtrs* __restrict__ geoms, const int32_t* __restrict__ vol_id,
+                                                   const int32_t* __restrict__ eb_id, const int32_t* __restrict__ face_id,
+                                                   const int32_t* __restrict__ box_id, const int64_t* __restrict__ counts,
+                                                   const int64_t* __restrict__ offs, int32_t* nrows, int32_t* maxrows,
+                                                   const int64_t* __restrict__ row_ptr, int32_t* col) {
+  using W = Win<D, R>;
+  __shared__ int8_t dist[W::NW];
+  const long long F = blockIdx.x;
+  if (F >= n_face) return;
+  const int lane = threadIdx.x;
+  const int32_t code = fcode[F];
+  const int gi = code >> 4, kind = (code >> 2) & 3, dn = code & 3;
+  const int32_t ref = fref[F];
+
+  const int32_t* vid = vol_id + gi * g.ncell;
+  const int32_t* eid = eb_id + gi * g.ncell;
+  const int32_t* fid = face_id + gi * g.NF;
+  const int32_t* bid = box_id + gi * g.NF;
+
+  // window origin and extents; the adjacent cells sit at normal index R (and R + 1)
+  int org[3] = {0, 0, 0}, ext[3] = {1, 1, 1};
+  int nrm = dn;
+  if (kind == 0) {
+    int j[3];
+    lattice_coords(g, dn, ref, j);
+    for (int ax = 0; ax < D; ++ax) {
+      ext[ax] = (ax == dn) ? W::EN : W::ET;
+      org[ax] = (ax == dn) ? j[ax] - R - 1 : j[ax] - R;
+    }
+  } else {
+    const int32_t c = geoms[gi].eb_cell[ref];
+    int ci[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+    nrm = 0;
+    for (int ax = 0; ax < D; ++ax) {
+      ext[ax] = (ax == 0) ? W::EN : W::ET;
+      org[ax] = ci[ax] - R;
+    }
+  }
+  const int NW = ext[0] * ext[1] * ext[2];
+
+  // per-lane window cells: global cell, volume flag, open faces to in-window neighbours
+  long long cell[W::K];
+  bool isvol[W::K];
+  unsigned open[W::K];
+  int wpos[W::K][3];
+#pragma unroll
+  for (int k = 0; k < W::K; ++k) {
+    const int w = lane + 64 * k;
+    isvol[k] = false;
+    open[k] = 0;
+    cell[k] = -1;
+    if (w >= NW) continue;
+    int wc[3] = {w % ext[0], (w / ext[0]) % ext[1], w / (ext[0] * ext[1])};
+    int x[3];
+    bool inbox = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      wpos[k][ax] = wc[ax];
+      x[ax] = org[ax] + wc[ax];
+      if (ax < D && (x[ax] < 0 || x[ax] >= g.n[ax])) inbox = false;
+    }
+    if (!inbox) continue;
+    cell[k] = cell_index(g, x);
+    isvol[k] = vid[cell[k]] >= 0;
+    if (!isvol[k]) continue;
+    for (int ax = 0; ax < D; ++ax)
+      for (int s = 0; s < 2; ++s) {
+        int wn = wc[ax] + (s ? 1 : -1);
+        if (wn < 0 || wn >= ext[ax]) continue;
+        int xn = x[ax] + (s ? 1 : -1);
+        if (xn < 0 || xn >= g.n[ax]) continue;
+        int j[3] = {x[0], x[1], x[2]};
+        j[ax] += s;
+        if (fid[lattice_index(g, ax, j)] >= 0) open[k] |= 1u << (2 * ax + s);
+      }
+  }
+  // distances: 0 at the adjacent volumes, R + 1 ("far") elsewhere
+#pragma unroll
+  for (int k = 0; k < W::K; ++k) {
+    const int w = lane + 64 * k;
+    if (w >= NW) continue;
+    bool adj = isvol[k];
+    for (int ax = 0; ax < D; ++ax) {
+      if (ax == nrm)
+        adj = adj && ((wpos[k][ax] == R) || (kind == 0 && wpos[k][ax] == R + 1));
+      else
+        adj = adj && (wpos[k][ax] == R);
+    }
+    dist[w] = adj ? 0 : (R + 1);
+  }
+  __syncthreads();
+  for (int r = 1; r <= R; ++r) {
+    int8_t nd[W::K];
+#pragma unroll
+    for (int k = 0; k < W::K; ++k) {
+      const int w = lane + 64 * k;
+      nd[k] = -1;
+      if (w >= NW || !isvol[k] || dist[w] <= R) continue;
+      const int st[3] = {1, ext[0], ext[0] * ext[1]};
+      for (int ax = 0; ax < D; ++ax)
+        for (int s = 0; s < 2; ++s)
+          if ((open[k] >> (2 * ax + s)) & 1u) {
+            int wn = w + (s ? st[ax] : -st[ax]);
+            if (dist[wn] == r - 1) nd[k] = (int8_t)r;
+          }
+    }
+#pragma unroll
+    for (int k = 0; k < W::K; ++k)
+      if (nd[k] > 0) dist[lane + 64 * k] = nd[k];
+    __syncthreads();
+  }
+  bool inS[W::K];
+#pragma unroll
+  for (int k = 0; k < W::K; ++k) {
+    const int w = lane + 64 * k;
+    inS[k] = (w < NW) && isvol[k] && dist[w] <= R;
+  }
+
+  const int64_t* cnt = counts + 4 * gi;
+  const int64_t phi0 = offs[gi];
+  if (!FILL) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < W::K; ++k) {
+      if (!inS[k]) continue;
+      c += 1;
+      c += eid[cell[k]] >= 0;
+      int x[3];
+      long long cc = cell[k];
+      x[0] = (int)(cc % g.n[0]); x[1] = (int)((cc / g.n[0]) % g.n[1]); x[2] = (int)(cc / ((long long)g.n[0] * g.n[1]));
+      for (int ax = 0; ax < D; ++ax)
+        for (int s = 0; s < 2; ++s) {
+          if (x[ax] != (s ? g.n[ax] - 1 : 0)) continue;
+          int j[3] = {x[0], x[1], x[2]};
+          j[ax] += s;
+          c += bid[lattice_index(g, ax, j)] >= 0;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if (lane == 0) {
+      nrows[F] = c;
+      atomicMax(maxrows, c);
+    }
+    return;
+  }
+  // fill in ascending Phi order: volumes, EB faces, box faces by (d, side)
+  long long pos = row_ptr[F];
+  const unsigned long long below = lanes_below(lane);
+#pragma unroll
+  for (int k = 0; k < W::K; ++k) {
+    bool p = inS[k];
+    unsigned long long m = __ballot(p);
+    if (p) col[pos + __popcll(m & below)] = (int32_t)(phi0 + vid[cell[k]]);
+    pos += __popcll(m);
+  }
+#pragma unroll
+  for (int k = 0; k < W::K; ++k) {
+    bool p = inS[k] && eid[cell[k]] >= 0;
+    unsigned long long m = __ballot(p);
+    if (p) col[pos + __popcll(m & below)] = (int32_t)(phi0 + cnt[0] + eid[cell[k]]);
+    pos += __popcll(m);
+  }
+  for (int ax = 0; ax < D; ++ax)
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int k = 0; k < W::K; ++k) {
+        int32_t b = -1;
+        if (inS[k]) {
+          long long cc = cell[k];
+          int x[3] = {(int)(cc % g.n[0]), (int)((cc / g.n[0]) % g.n[1]), (int)(cc / ((long long)g.n[0] * g.n[1]))};
+          if (x[ax] == (s ? g.n[ax] - 1 : 0)) {
+            int j[3] = {x[0], x[1], x[2]};
+            j[ax] += s;
+            b = bid[lattice_index(g, ax, j)];
+          }
+        }
+        bool p = b >= 0;
+        unsigned long long m = __ballot(p);
+        if (p) col[pos + __popcll(m & below)] = (int32_t)(phi0 + cnt[0] + cnt[1] + b);
+        pos += __popcll(m);
+      }
+    }
+}
+
+template <int D, int R>
+static void launch_neighbours(const Work& w, long long n_face, const int64_t* row_ptr, int32_t* col, bool fill,
+                              hipStream_t st) {
+  if (fill)
+    hipLaunchKernelGGL((k_neighbours<D, R, true>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
+                       w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.nrows,
+                       w.bins + 2 * kNBuckets, row_ptr, col);
+  else
+    hipLaunchKernelGGL((k_neighbours<D, R, false>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
+                       w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.nrows,
+                       w.bins + 2 * kNBuckets, row_ptr, col);
+}
+
+int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const int64_t* row_ptr, int32_t* col,
+                   bool fill, hipStream_t st) {
+  if (n_face <= 0) return CUTCELL_OK;
+  if (!fill)
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins + 2 * kNBuckets, 1LL, 0);
+  const int D = o.dim, R = o.path_radius;
+#define CC_NB(DD, RR) \
+  if (D == DD && R == RR) { launch_neighbours<DD, RR>(w, n_face, row_ptr, col, fill, st); }
+  CC_NB(2, 1) CC_NB(2, 2) CC_NB(2, 3) CC_NB(2, 4) CC_NB(3, 1) CC_NB(3, 2) CC_NB(3, 3) CC_NB(3, 4)
+#undef CC_NB
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// volume -> faces table and the 1/|V| scale of the divergence
+
+__global__ void k_volume_tables(GridDims g, int G, int M, double hD, const GeomPtrs* __restrict__ geoms,
+                                const int32_t* __restrict__ vol_id, const int32_t* __restrict__ eb_id,
+                                const int32_t* __restrict__ face_id, const int64_t* __restrict__ counts,
+                                const int64_t* __restrict__ offs, int32_t* vol_face, double* vol_scale) {
+  const int gi = blockIdx.y;
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const int32_t v = vol_id[gi * g.ncell + c];
+  if (v < 0) return;
+  const int D = g.D;
+  const long long V = offs[(G + 1) + gi] + v;
+  const long long F0 = offs[2 * (G + 1) + gi];
+  int x[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+  const int S = 2 * D + 1;
+  for (int d = 0; d < D; ++d)
+    for (int s = 0; s < 2; ++s) {
+      int j[3] = {x[0], x[1], x[2]};
+      j[d] += s;
+      int32_t f = face_id[gi * g.NF + lattice_index(g, d, j)];
+      vol_face[V * S + 2 * d + s] = (f >= 0) ? (int32_t)(F0 + f) : -1;
+    }
+  int32_t e = eb_id[gi * g.ncell + c];
+  vol_face[V * S + 2 * D] = (e >= 0) ? (int32_t)(F0 + counts[4 * gi + 3] + e) : -1;
+  vol_scale[V] = 1.0 / (geoms[gi].vol_mom[c * M] * hD);
+}
+
+int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, int32_t* vol_face, double* vol_scale,
+                  hipStream_t st) {
+  if (n_vol_total <= 0) return CUTCELL_OK;
+  const int M = binom(o.order + o.dim, o.dim);
+  double hD = 1.0;
+  for (int d = 0; d < o.dim; ++d) hD *= o.h;
+  hipLaunchKernelGGL(k_volume_tables, dim3(blocks_for(w.dims.ncell, 256), w.G), dim3(256), 0, st, w.dims, w.G, M, hD,
+                     w.geoms, w.vol_id, w.eb_id, w.face_id, w.counts, w.offs, vol_face, vol_scale);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// binning by row count: buckets of 16 rows (N <= 16, ..., <= 128) and one bucket for
+// faces with fewer rows than monomials; perm lists faces bucket by bucket
+
+__global__ void k_bin_count(long long n_face, int M, const int32_t* __restrict__ nrows, int32_t* bins) {
+  long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (f >= n_face) return;
+  const int N = nrows[f];
+  const int b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
+  atomicAdd(&bins[b], 1);
+}
+
+__global__ void k_bin_starts(int32_t* bins) {
+  if (threadIdx.x != 0) return;
+  int s = 0;
+  for (int b = 0; b < kNBuckets; ++b) {
+    bins[kNBuckets + b] = s;
+    s += bins[b];
+  }
+}
+
+__global__ void k_bin_scatter(long long n_face, int M, const int32_t* __restrict__ nrows, int32_t* bins,
+                              int32_t* perm) {
+  long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (f >= n_face) return;
+  const int N = nrows[f];
+  const int b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
+  perm[atomicAdd(&bins[kNBuckets + b], 1)] = (int32_t)f;
+}
+
+int bin_faces(const Work& w, long long n_face, int M, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins, (long long)(2 * kNBuckets), 0);
+  if (n_face <= 0) return CUTCELL_OK;
+  hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, w.bins);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, st, w.bins);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, w.bins,
+                     w.perm);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+}  // namespace cutcell

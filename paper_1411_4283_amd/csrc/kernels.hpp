@@ -1,0 +1,68 @@
+// Device workspace layout and kernel launchers shared by the host entry points.
+#pragma once
+
+#include "common.hpp"
+
+namespace cutcell {
+
+// flux-face code: geometry << 4 | kind << 2 | direction (kind 0 grid/box, 1 EB)
+__host__ __device__ inline int32_t face_code(int g, int kind, int d) { return (g << 4) | (kind << 2) | d; }
+
+constexpr int kMaxBins = 8;     // row-count bins of 16 rows: N <= 16, 32, ..., 128
+constexpr int kBinRows = 16;
+constexpr int kMaxRows = kMaxBins * kBinRows;
+constexpr int kNBuckets = kMaxBins + 1;   // the last bucket holds faces with N < M
+constexpr int kBinWords = 2 * kNBuckets + 1;  // counts, cursors, max rows
+
+// Per-batch workspace: pointers into the caller's buffer.
+struct Work {
+  GridDims dims;
+  int G;
+  long long L;          // enumeration flag space per geometry: cells | box slots | lattice faces
+  long long maxface;    // flux-face capacity per geometry (lattice faces + one EB per cell)
+  int32_t* flags;       // [G][L]
+  int32_t* excl;        // [G][L]
+  int32_t* seg_total;   // [G]
+  int32_t* scan_tmp;    // [G][tiles(L)]
+  int32_t* vol_id;      // [G][ncell]  local volume index or -1
+  int32_t* eb_id;       // [G][ncell]  local EB index or -1
+  int32_t* face_id;     // [G][NF]     local flux-face index or -1
+  int32_t* box_id;      // [G][NF]     local box-face index or -1
+  int32_t* box_lf;      // [G][nboxslot] lattice face of each local box face
+  int32_t* vol_cell;    // [G][ncell]  cell of each local volume
+  int64_t* counts;      // [G][4]      n_vol, n_eb, n_box, n_gface
+  int64_t* offs;        // [3][G+1]    phi_off, vol_off, face_off
+  int32_t* fcode;       // [G*maxface] per global flux face
+  int32_t* fref;        // [G*maxface] lattice face (grid/box) or EB index
+  int32_t* nrows;       // [G*maxface]
+  int64_t* scan64;      // int64 scan tiles over G*maxface
+  int64_t* rp_tmp;      // [G*maxface + 1] row offsets when the caller has none (query)
+  int32_t* perm;        // [G*maxface]
+  int32_t* bins;        // [kBinWords] bucket counts, bucket cursors, max rows
+  int32_t* flagged;     // [1]
+  GeomPtrs* geoms;      // [G]
+  size_t bytes;
+};
+
+size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w);
+
+// enumeration (Sec. 2.1): flags, maps, global face table, counts and offsets
+int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st);
+// neighbour rows (Sec. 2.4): count (fill = false) or write col[] (fill = true)
+int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const int64_t* row_ptr, int32_t* col,
+                   bool fill, hipStream_t st);
+// volume -> face table and 1/(kappa h^D)
+int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, int32_t* vol_face,
+                  double* vol_scale, hipStream_t st);
+// binning by row count and the stencil solves (Sec. 2.2.1)
+int bin_faces(const Work& w, long long n_face, int M, hipStream_t st);
+int solve_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count /* host */, long long n_face,
+                   const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st);
+// operator apply (Sec. 2.2, Sec. 3.3)
+int apply_operator(int D, long long n_face, long long n_vol, const int64_t* row_ptr, const int32_t* col,
+                   const double* val, const int32_t* vol_face, const double* vol_scale, const double* phi,
+                   double* lphi, double* flux, double* flux_tmp, hipStream_t st);
+
+__global__ void k_fill_i32(int32_t* p, long long n, int32_t v);
+
+}  // namespace cutcell
