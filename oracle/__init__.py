@@ -31,3 +31,4 @@ from .stencils import (  # noqa: F401
     STATUS_RANK_DEFICIENT,
     STATUS_NONFINITE,
 )
+from .adjoint import apply_adjoint, stencils_backward  # noqa: F401,E402
