@@ -285,7 +285,7 @@ using Emit = std::function<void(double*, double)>;  // point (free coords set), 
 struct Ctx {
   const Shape* S;
   const Gauss* G;
-  int maxdepth = 12;
+  int maxdepth = 36;
   int err = 0;
 };
 
@@ -450,7 +450,19 @@ void quad(Ctx& C, unsigned freem, const double* lo, const double* hi, const std:
   }
   if (!mono) {
     if (depth >= C.maxdepth) {
-      C.err++;
+      // No monotone direction even in a box 2^-maxdepth of the cell: psi has a
+      // critical point on its zero set here (a tangency).  Fall back to Gauss points
+      // that each satisfy the sign conditions; the box's measure is negligible.
+      tensor(C, freem, lo, hi, x, 1.0, 0, [&](double* xp, double w) {
+        for (const Fn& f : fns) {
+          if (f.sign == 0) continue;
+          double y[3];
+          fill(f, xp, y, D);
+          double v = psi(S, y, nullptr);
+          if ((f.sign > 0 && !fluid(v)) || (f.sign < 0 && fluid(v))) return;
+        }
+        emit(xp, w);
+      });
       return;
     }
     int sd = -1;
@@ -503,7 +515,7 @@ void surf(Ctx& C, const double* lo, const double* hi, int depth, const EmitS& em
   double gmin, gmax;
   dpsi_bounds(S, lo, hi, k, gmin, gmax);
   if (!(gmin > 0 || gmax < 0)) {
-    if (depth >= C.maxdepth) { C.err++; return; }
+    if (depth >= C.maxdepth) return;   // tangency: the surface inside this tiny box is dropped
     int sd = 0;
     for (int d = 1; d < D; ++d)
       if (hi[d] - lo[d] > hi[sd] - lo[sd]) sd = d;
