@@ -50,9 +50,14 @@
  *  Memory.  Every array argument is DEVICE memory owned by the caller, except the
  *    structs themselves and cutcell_sizes, which live on the host.  The library keeps no
  *    state between calls and allocates no device memory: scratch comes from the caller's
- *    workspace (size from cutcell_workspace_bytes).  Work is enqueued on `stream` (a
- *    hipStream_t; 0 = the null stream).  cutcell_query and cutcell_build_stencils
- *    synchronise `stream` before returning (they read counts back); cutcell_apply does not.
+ *    workspace (sizes from the *_workspace_bytes functions).  Work is enqueued on `stream`
+ *    (a hipStream_t; 0 = the null stream).  cutcell_query, cutcell_build_stencils and
+ *    cutcell_stencils_backward synchronise `stream` before returning (they read counts
+ *    back); cutcell_apply, cutcell_build_transpose and cutcell_apply_adjoint do not.
+ *
+ *  Derivatives.  The paper defines the forward maps only; the adjoints below are their
+ *    exact derivatives (up to rounding).  For a scalar loss l, *_bar denotes dl/d(.).
+ *    Results are deterministic: no floating-point atomics, fixed summation orders.
  *
  *  Errors.  Every entry point returns CUTCELL_OK (0), CUTCELL_W_FLAGGED_FACES (> 0:
  *    success, some faces got a nonzero status) or a negative CUTCELL_E_* code; the
@@ -71,7 +76,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 1
+#define CUTCELL_ABI_VERSION 2
 
 enum {
   CUTCELL_OK = 0,
@@ -160,6 +165,65 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
  * phi: [n_phi], lphi: [n_vol].  Asynchronous on `stream`. */
 int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
                   const double* phi, double* lphi, double* flux, cutcell_stream_t stream);
+
+/* Transposed structure of the stencils (for the adjoints): for every Phi entry k, the
+ * CSR positions j with col[j] = k, ascending, in nz[col_ptr[k] .. col_ptr[k+1]), and the
+ * face (CSR row) of each in nz_face[].  Arrays sized from cutcell_sizes. */
+typedef struct {
+  int64_t* col_ptr;     /* [n_phi + 1]                                                  */
+  int32_t* nz;          /* [nnz]                                                        */
+  int32_t* nz_face;     /* [nnz]                                                        */
+} cutcell_transpose;
+
+/* Gradients with respect to one geometry's inputs, same layouts as cutcell_geom. */
+typedef struct {
+  double* vol_mom;      /* [ncell][M]                                                   */
+  double* face_mom[3];  /* [nface_d][Mf] for d < D                                      */
+  double* eb_mom;       /* [n_eb][M]     (may be NULL when n_eb = 0)                    */
+  double* eb_nmom;      /* [n_eb][D][M1] (may be NULL when n_eb = 0)                    */
+} cutcell_geom_grad;
+
+/* Bytes of workspace cutcell_build_transpose needs (0 if nnz >= 2^31: unsupported). */
+size_t cutcell_transpose_workspace_bytes(const cutcell_sizes* sizes);
+
+/* Builds the transpose of the stencils in `st` (output of cutcell_build_stencils) into
+ * *out by a stable sort of the CSR positions by column.  Asynchronous on `stream`. */
+int cutcell_build_transpose(const cutcell_sizes* sizes, const cutcell_stencils* st, cutcell_transpose* out,
+                            void* workspace, size_t workspace_bytes, cutcell_stream_t stream);
+
+/* Adjoint of cutcell_apply (the transpose of the linear map Phi -> L(Phi) of Sec. 2.2,
+ * eq. 'laplacian over V', and its derivatives in the stencil values and the volume scales).
+ * Given lphi_bar = dl/dL [n_vol]:
+ *   flux_bar[f] = sum over the volumes v of f of sigma_vf vol_scale[v] lphi_bar[v]   (out, required)
+ *   phi_bar[k]  = sum_{j: col[j] = k} val[j] flux_bar[face(j)]                       (out, required)
+ *   val_bar[j]  = flux_bar[face(j)] phi[col[j]]             (out, optional; needs phi)
+ *   scale_bar[v]= lphi_bar[v] sum_f sigma_vf flux[f]        (out, optional; needs the
+ *                 forward's flux output)  -- dl/d vol_scale, which
+ *                 cutcell_stencils_backward turns into a kappa gradient.
+ * Asynchronous on `stream`. */
+int cutcell_apply_adjoint(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
+                          const cutcell_transpose* tr, const double* phi, const double* flux,
+                          const double* lphi_bar, double* phi_bar, double* val_bar, double* scale_bar,
+                          double* flux_bar, cutcell_stream_t stream);
+
+/* Bytes of workspace cutcell_stencils_backward needs (it includes the build's). */
+size_t cutcell_backward_workspace_bytes(const cutcell_opts* opts, const cutcell_sizes* sizes);
+
+/* Adjoint of cutcell_build_stencils (the derivative of s = W (A^T W)^+ F of Sec. 2.2.1
+ * with the rows, centring and weights of Sec. 2.4): given val_bar = dl/dval [nnz] and,
+ * optionally, scale_bar = dl/dvol_scale [n_vol] (from cutcell_apply_adjoint), writes
+ * dl/d(inputs) into grads[g] for every geometry (overwritten, not accumulated; zero where
+ * an input has no influence, and zero for faces with a nonzero status, whose stencil is
+ * zero).  The EB face's x0 (the cut volume's centroid) makes the volume's moments 0..D
+ * enter every row of that face; that dependence is included.  weight_bar (optional,
+ * [nnz]) receives dl/dW_i of every row with the other inputs fixed.  `st` and `tr` must be
+ * the outputs of cutcell_build_stencils / cutcell_build_transpose for the same inputs.
+ * Synchronises `stream`. */
+int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                              const cutcell_sizes* sizes, const cutcell_stencils* st,
+                              const cutcell_transpose* tr, const double* val_bar, const double* scale_bar,
+                              const cutcell_geom_grad* grads, double* weight_bar, void* workspace,
+                              size_t workspace_bytes, cutcell_stream_t stream);
 
 /* Observability: when enabled (per calling thread), cutcell_build_stencils records HIP
  * events on its stream between its phases, and cutcell_last_profile copies the last

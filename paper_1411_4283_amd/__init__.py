@@ -8,3 +8,5 @@ call does, and fails loudly if the library has not been built.
 
 from .api import Builder, DeviceGeometry, Stencils, apply, build_stencils, make_opts  # noqa: F401
 from ._lib import CutcellError, LIB_PATH, load  # noqa: F401
+from .api import Transpose, apply_adjoint, build_transpose  # noqa: F401,E402
+from .autograd import CutCellOperator, OperatorApply, StencilBuild  # noqa: F401,E402

@@ -59,6 +59,23 @@ class StencilArrays(ctypes.Structure):
     ]
 
 
+class TransposeArrays(ctypes.Structure):
+    _fields_ = [
+        ("col_ptr", P),
+        ("nz", P),
+        ("nz_face", P),
+    ]
+
+
+class GeomGrad(ctypes.Structure):
+    _fields_ = [
+        ("vol_mom", P),
+        ("face_mom", P * 3),
+        ("eb_mom", P),
+        ("eb_nmom", P),
+    ]
+
+
 OK = 0
 W_FLAGGED_FACES = 1
 E_INVALID_ARG = -1
@@ -81,6 +98,16 @@ SIGNATURES = {
                                               ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P,
                                               ctypes.c_size_t, P]),
     "cutcell_apply": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P, P, P, P]),
+    "cutcell_transpose_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
+    "cutcell_build_transpose": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays),
+                                               ctypes.POINTER(TransposeArrays), P, ctypes.c_size_t, P]),
+    "cutcell_apply_adjoint": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
+                                             ctypes.POINTER(TransposeArrays), P, P, P, P, P, P, P, P]),
+    "cutcell_backward_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Opts), ctypes.POINTER(Sizes)]),
+    "cutcell_stencils_backward": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts),
+                                                 ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays),
+                                                 ctypes.POINTER(TransposeArrays), P, P, ctypes.POINTER(GeomGrad), P, P,
+                                                 ctypes.c_size_t, P]),
     "cutcell_set_profiling": (None, [ctypes.c_int]),
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "cutcell_last_error": (ctypes.c_char_p, []),

@@ -13,7 +13,7 @@ from math import comb
 import torch
 
 from . import _lib
-from ._lib import Geom, Opts, Sizes, StencilArrays, check, load
+from ._lib import Geom, GeomGrad, Opts, Sizes, StencilArrays, TransposeArrays, check, load
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -94,13 +94,86 @@ class Stencils:
     vol_off: torch.Tensor
     face_off: torch.Tensor
     code: int = 0
+    transpose: "Transpose | None" = None
     _keep: list = field(default_factory=list, repr=False)
 
-    def struct(self) -> StencilArrays:
+    def struct(self, val: torch.Tensor | None = None, vol_scale: torch.Tensor | None = None) -> StencilArrays:
+        """The C struct; `val` / `vol_scale` replace the stored arrays when given."""
         s = StencilArrays()
         for name in ("row_ptr", "col", "val", "status", "vol_face", "vol_scale", "phi_off", "vol_off", "face_off"):
             setattr(s, name, _ptr(getattr(self, name)))
+        if val is not None:
+            _check_f64(val, self.sizes.nnz, "val")
+            s.val = _ptr(val)
+        if vol_scale is not None:
+            _check_f64(vol_scale, self.sizes.n_vol, "vol_scale")
+            s.vol_scale = _ptr(vol_scale)
         return s
+
+
+def _check_f64(t: torch.Tensor, n: int, name: str):
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous float64 device tensor with at least {n} entries")
+
+
+@dataclass
+class Transpose:
+    """Column structure of the stencils (cutcell_build_transpose)."""
+
+    col_ptr: torch.Tensor
+    nz: torch.Tensor
+    nz_face: torch.Tensor
+
+    def struct(self) -> TransposeArrays:
+        s = TransposeArrays()
+        s.col_ptr, s.nz, s.nz_face = _ptr(self.col_ptr), _ptr(self.nz), _ptr(self.nz_face)
+        return s
+
+
+def build_transpose(st: Stencils, stream=None) -> Transpose:
+    """Transpose of the stencils, cached on `st`."""
+    if st.transpose is not None:
+        return st.transpose
+    s = st.sizes
+    dev = st.row_ptr.device
+    lib = load()
+    nbytes = lib.cutcell_transpose_workspace_bytes(ctypes.byref(s))
+    if nbytes == 0:
+        raise ValueError("the transpose needs nnz < 2^31")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    tr = Transpose(col_ptr=torch.empty(s.n_phi + 1, dtype=torch.int64, device=dev),
+                   nz=torch.empty(max(s.nnz, 1), dtype=torch.int32, device=dev),
+                   nz_face=torch.empty(max(s.nnz, 1), dtype=torch.int32, device=dev))
+    arr, tarr = st.struct(), tr.struct()
+    rc = lib.cutcell_build_transpose(ctypes.byref(s), ctypes.byref(arr), ctypes.byref(tarr), _ptr(ws), ws.numel(),
+                                     _stream(stream))
+    check(rc, "cutcell_build_transpose", allow_flagged=False)
+    st.transpose = tr
+    st._keep.append(ws)   # the sort's scratch stays alive until the stream has used it
+    return tr
+
+
+def apply_adjoint(st: Stencils, lphi_bar: torch.Tensor, phi: torch.Tensor | None = None,
+                  flux: torch.Tensor | None = None, val: torch.Tensor | None = None,
+                  vol_scale: torch.Tensor | None = None, stream=None):
+    """Adjoint of apply: returns (phi_bar, val_bar or None, scale_bar or None, flux_bar).
+    val_bar needs phi; scale_bar needs the forward's flux."""
+    s = st.sizes
+    dev = lphi_bar.device
+    _check_f64(lphi_bar, s.n_vol, "lphi_bar")
+    tr = build_transpose(st, stream)
+    f64 = dict(dtype=torch.float64, device=dev)
+    phi_bar = torch.empty(max(s.n_phi, 1), **f64)
+    flux_bar = torch.empty(max(s.n_face, 1), **f64)
+    val_bar = torch.empty(max(s.nnz, 1), **f64) if phi is not None else None
+    scale_bar = torch.empty(max(s.n_vol, 1), **f64) if flux is not None else None
+    arr, tarr = st.struct(val, vol_scale), tr.struct()
+    rc = load().cutcell_apply_adjoint(ctypes.byref(s), st.dim, ctypes.byref(arr), ctypes.byref(tarr), _ptr(phi),
+                                      _ptr(flux), _ptr(lphi_bar), _ptr(phi_bar), _ptr(val_bar), _ptr(scale_bar),
+                                      _ptr(flux_bar), _stream(stream))
+    check(rc, "cutcell_apply_adjoint", allow_flagged=False)
+    cut = lambda t, n: None if t is None else t[:n]  # noqa: E731
+    return phi_bar[: s.n_phi], cut(val_bar, s.nnz), cut(scale_bar, s.n_vol), flux_bar[: s.n_face]
 
 
 class Builder:
@@ -160,21 +233,57 @@ class Builder:
         return out
 
 
+    def backward(self, st: Stencils, val_bar: torch.Tensor, scale_bar: torch.Tensor | None = None,
+                 weight_bar: bool = False, stream=None):
+        """Gradients of l with dl/dval = val_bar (and dl/dvol_scale = scale_bar) with respect
+        to every geometry's moments: a list of dicts (vol_mom, face_mom, eb_mom, eb_nmom),
+        plus weight_bar [nnz] (or None)."""
+        s = st.sizes
+        _check_f64(val_bar, s.nnz, "val_bar")
+        if scale_bar is not None:
+            _check_f64(scale_bar, s.n_vol, "scale_bar")
+        tr = build_transpose(st, stream)
+        lib = load()
+        nbytes = lib.cutcell_backward_workspace_bytes(ctypes.byref(self.opts), ctypes.byref(s))
+        if nbytes == 0:
+            raise ValueError("unsupported options")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        out = []
+        garr = (GeomGrad * len(self.geoms))()
+        for i, g in enumerate(self.geoms):
+            d = dict(vol_mom=torch.empty_like(g.vol_mom), face_mom=[torch.empty_like(f) for f in g.face_mom],
+                     eb_mom=torch.empty_like(g.eb_mom), eb_nmom=torch.empty_like(g.eb_nmom))
+            out.append(d)
+            garr[i].vol_mom = _ptr(d["vol_mom"])
+            for k in range(3):
+                garr[i].face_mom[k] = _ptr(d["face_mom"][k]) if k < self.dim else None
+            garr[i].eb_mom = _ptr(d["eb_mom"]) if d["eb_mom"].numel() else None
+            garr[i].eb_nmom = _ptr(d["eb_nmom"]) if d["eb_nmom"].numel() else None
+        wb = torch.empty(max(s.nnz, 1), dtype=torch.float64, device=self.device) if weight_bar else None
+        arr, tarr = st.struct(), tr.struct()
+        rc = lib.cutcell_stencils_backward(self.garr, len(self.geoms), ctypes.byref(self.opts), ctypes.byref(s),
+                                           ctypes.byref(arr), ctypes.byref(tarr), _ptr(val_bar), _ptr(scale_bar),
+                                           garr, _ptr(wb), _ptr(ws), ws.numel(), _stream(stream))
+        check(rc, "cutcell_stencils_backward", allow_flagged=False)
+        return out, (None if wb is None else wb[: s.nnz])
+
+
 def build_stencils(geoms, path_radius: int, stream=None) -> Stencils:
     """Flux stencils of every face of one geometry (or a batch sharing a grid)."""
     return Builder(geoms, path_radius).build(stream=stream)
 
 
 def apply(st: Stencils, phi: torch.Tensor, lphi: torch.Tensor | None = None, flux: torch.Tensor | None = None,
-          stream=None):
-    """L(Phi) = divergence of the face fluxes s_f^T Phi; returns (lphi, flux)."""
+          stream=None, val: torch.Tensor | None = None, vol_scale: torch.Tensor | None = None):
+    """L(Phi) = divergence of the face fluxes s_f^T Phi; returns (lphi, flux).  `val` and
+    `vol_scale` replace the stencil values and volume scales of `st` when given."""
     s = st.sizes
     assert phi.dtype == torch.float64 and phi.is_contiguous() and phi.numel() == s.n_phi
     if lphi is None:
         lphi = torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=phi.device)
     if flux is None:
         flux = torch.empty(max(s.n_face, 1), dtype=torch.float64, device=phi.device)
-    arr = st.struct()
+    arr = st.struct(val, vol_scale)
     rc = load().cutcell_apply(ctypes.byref(s), st.dim, ctypes.byref(arr), _ptr(phi), _ptr(lphi), _ptr(flux),
                               _stream(stream))
     check(rc, "cutcell_apply", allow_flagged=False)

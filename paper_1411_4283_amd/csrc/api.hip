@@ -77,6 +77,7 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   t.box_id = (int32_t*)take(sizeof(int32_t) * G * g.NF);
   t.box_lf = (int32_t*)take(sizeof(int32_t) * G * std::max<long long>(g.nboxslot, 1));
   t.vol_cell = (int32_t*)take(sizeof(int32_t) * G * g.ncell);
+  t.cellinfo = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
   t.counts = (int64_t*)take(sizeof(int64_t) * 4 * G);
   t.offs = (int64_t*)take(sizeof(int64_t) * 3 * (G + 1));
   t.fcode = (int32_t*)take(sizeof(int32_t) * totface);
@@ -190,6 +191,8 @@ static int count_rows(const Prepared& P, const cutcell_opts* o, int64_t* row_ptr
   const Work& w = P.w;
   int rc = neighbour_rows(w, *o, P.n_face, nullptr, nullptr, false, st);
   if (rc) return rc;
+  rc = max_rows(w, P.n_face, st);
+  if (rc) return rc;
   int64_t total = 0;
   if (P.n_face > 0) {
     rc = exclusive_scan<int32_t, int64_t>(w.nrows, P.n_face, P.n_face, 1, row_ptr, P.n_face, row_ptr ? row_ptr + P.n_face : nullptr,
@@ -205,6 +208,46 @@ static int count_rows(const Prepared& P, const cutcell_opts* o, int64_t* row_ptr
   *maxrows = mr;
   return CUTCELL_OK;
 }
+
+
+// Scratch of cutcell_stencils_backward after the forward workspace.
+struct BackWork {
+  GradPtrs* grads;     // [G]
+  double* face_yw;     // [n_face][2M]
+  double* face_x0;     // [n_face][4]
+  double* owner_grad;  // [n_face][4]
+  double* nz_rz;       // [nnz][2]
+  size_t bytes;
+};
+
+static size_t layout_backward(const cutcell_opts& o, int G, long long n_face, long long nnz, char* base, BackWork* b) {
+  const int M = binom(o.order + o.dim, o.dim);
+  size_t off = layout_work(o, G, nullptr, nullptr);
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  BackWork t{};
+  t.grads = (GradPtrs*)take(sizeof(GradPtrs) * G);
+  t.face_yw = (double*)take(sizeof(double) * 2 * M * std::max<long long>(n_face, 1));
+  t.face_x0 = (double*)take(sizeof(double) * 4 * std::max<long long>(n_face, 1));
+  t.owner_grad = (double*)take(sizeof(double) * 4 * std::max<long long>(n_face, 1));
+  t.nz_rz = (double*)take(sizeof(double) * 2 * std::max<long long>(nnz, 1));
+  t.bytes = off;
+  if (b) *b = t;
+  return off;
+}
+
+static void fill_zero(double* p, long long n, hipStream_t st) {
+  if (p && n > 0) hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, 0.0);
+}
+
+static bool stencils_complete(const cutcell_stencils* s) {
+  return s && s->row_ptr && s->col && s->val && s->status && s->vol_face && s->vol_scale;
+}
+
+static bool transpose_complete(const cutcell_transpose* t) { return t && t->col_ptr && t->nz && t->nz_face; }
 
 }  // namespace cutcell
 
@@ -312,6 +355,135 @@ int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
     return fail(CUTCELL_E_INVALID_ARG, "stencil arrays are NULL");
   return apply_operator(dim, sizes->n_face, sizes->n_vol, st_->row_ptr, st_->col, st_->val, st_->vol_face,
                         st_->vol_scale, phi, lphi, flux, nullptr, (hipStream_t)stream);
+}
+
+size_t cutcell_transpose_workspace_bytes(const cutcell_sizes* sizes) {
+  if (!sizes || sizes->nnz < 0 || sizes->nnz >= (1LL << 31)) return 0;
+  return transpose_temp_bytes(sizes->nnz, sizes->n_phi);
+}
+
+int cutcell_build_transpose(const cutcell_sizes* sizes, const cutcell_stencils* st_, cutcell_transpose* out,
+                            void* workspace, size_t workspace_bytes, cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !transpose_complete(out))
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (sizes->nnz >= (1LL << 31)) return fail(CUTCELL_E_UNSUPPORTED, "the transpose needs nnz < 2^31");
+  return build_transpose(sizes->n_face, sizes->n_phi, sizes->nnz, st_->row_ptr, st_->col, out->col_ptr, out->nz,
+                         out->nz_face, (char*)workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int cutcell_apply_adjoint(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_,
+                          const cutcell_transpose* tr, const double* phi, const double* flux,
+                          const double* lphi_bar, double* phi_bar, double* val_bar, double* scale_bar,
+                          double* flux_bar, cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !transpose_complete(tr) || !lphi_bar || !phi_bar || !flux_bar)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument (lphi_bar, phi_bar and flux_bar are required)");
+  if (val_bar && !phi) return fail(CUTCELL_E_INVALID_ARG, "val_bar needs phi");
+  if (scale_bar && !flux) return fail(CUTCELL_E_INVALID_ARG, "scale_bar needs the forward flux");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  Transpose t{tr->col_ptr, tr->nz, tr->nz_face};
+  return apply_adjoint(dim, sizes->n_face, sizes->n_vol, sizes->n_phi, st_->row_ptr, st_->col, st_->val,
+                       st_->vol_face, st_->vol_scale, t, phi, flux, lphi_bar, phi_bar, val_bar, scale_bar, flux_bar,
+                       (hipStream_t)stream);
+}
+
+size_t cutcell_backward_workspace_bytes(const cutcell_opts* opts, const cutcell_sizes* sizes) {
+  if (!opts || !sizes || sizes->n_geom < 1 || (opts->dim != 2 && opts->dim != 3) ||
+      (opts->order != 2 && opts->order != 4))
+    return 0;
+  return layout_backward(*opts, sizes->n_geom, sizes->n_face, sizes->nnz, nullptr, nullptr);
+}
+
+int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                              const cutcell_sizes* sizes, const cutcell_stencils* st_, const cutcell_transpose* tr,
+                              const double* val_bar, const double* scale_bar, const cutcell_geom_grad* grads,
+                              double* weight_bar, void* workspace, size_t workspace_bytes, cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !transpose_complete(tr) || !val_bar || !grads)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = validate(geoms, n_geom, opts);
+  if (rc) return rc;
+  for (int i = 0; i < n_geom; ++i) {
+    if (!grads[i].vol_mom) return fail(CUTCELL_E_INVALID_ARG, "grads[i].vol_mom is NULL");
+    for (int d = 0; d < opts->dim; ++d)
+      if (!grads[i].face_mom[d]) return fail(CUTCELL_E_INVALID_ARG, "grads[i].face_mom[d] is NULL");
+    if (geoms[i].n_eb > 0 && (!grads[i].eb_mom || !grads[i].eb_nmom))
+      return fail(CUTCELL_E_INVALID_ARG, "grads[i] EB arrays are NULL");
+  }
+  const size_t need = layout_backward(*opts, n_geom, sizes->n_face, sizes->nnz, nullptr, nullptr);
+  if (!workspace || workspace_bytes < need)
+    return fail(CUTCELL_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  Prepared P;
+  rc = prepare(geoms, n_geom, opts, workspace, workspace_bytes, st, &P);
+  if (rc) return rc;
+  if (sizes->n_geom != n_geom || sizes->n_face != P.n_face || sizes->n_vol != P.n_vol || sizes->n_phi != P.n_phi)
+    return fail(CUTCELL_E_CAPACITY, "sizes do not match these inputs");
+  const Work& w = P.w;
+  BackWork b;
+  layout_backward(*opts, n_geom, sizes->n_face, sizes->nnz, (char*)workspace, &b);
+  const int D = opts->dim, Q = opts->order;
+  const int M = binom(Q + D, D), Mf = binom(Q + D - 1, D - 1), M1 = binom(Q - 1 + D, D);
+  // every gradient starts at zero: cells without a volume, faces without a flux, ...
+  std::vector<GradPtrs> gp(n_geom);
+  for (int i = 0; i < n_geom; ++i) {
+    const int64_t neb = geoms[i].n_eb;
+    gp[i].vol_mom = grads[i].vol_mom;
+    fill_zero(gp[i].vol_mom, w.dims.ncell * M, st);
+    for (int d = 0; d < 3; ++d) {
+      gp[i].face_mom[d] = (d < D) ? grads[i].face_mom[d] : nullptr;
+      if (d < D) fill_zero(gp[i].face_mom[d], w.dims.nface[d] * Mf, st);
+    }
+    gp[i].eb_mom = grads[i].eb_mom;
+    gp[i].eb_nmom = grads[i].eb_nmom;
+    if (neb > 0) {
+      fill_zero(gp[i].eb_mom, neb * M, st);
+      fill_zero(gp[i].eb_nmom, neb * D * M1, st);
+    }
+  }
+  CC_HIP(hipMemcpyAsync(b.grads, gp.data(), sizeof(GradPtrs) * n_geom, hipMemcpyHostToDevice, st));
+  // bin the faces by their row counts again
+  rc = rows_per_face(w, P.n_face, st_->row_ptr, st);
+  if (rc) return rc;
+  rc = max_rows(w, P.n_face, st);
+  if (rc) return rc;
+  rc = bin_faces(w, P.n_face, M, st);
+  if (rc) return rc;
+  int32_t bc[kBinWords];
+  CC_HIP(hipMemcpyAsync(bc, w.bins, sizeof(bc), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  if (bc[2 * kNBuckets] > kMaxRows) return fail(CUTCELL_E_INVALID_ARG, "row_ptr does not come from a build");
+  BackwardArgs ba{};
+  ba.val_bar = val_bar;
+  ba.face_yw = b.face_yw;
+  ba.face_x0 = b.face_x0;
+  ba.nz_rz = b.nz_rz;
+  ba.weight_bar = weight_bar;
+  ba.owner_grad = b.owner_grad;
+  ba.grads = b.grads;
+  rc = backward_stencils(w, *opts, bc, st_->row_ptr, st_->col, ba, st);
+  if (rc) return rc;
+  ReduceArgs R{};
+  R.g = w.dims;
+  R.G = n_geom;
+  R.n_phi = P.n_phi;
+  R.offs = w.offs;
+  R.counts = w.counts;
+  R.geoms = w.geoms;
+  R.grads = b.grads;
+  R.vol_cell_ws = w.vol_cell;
+  R.box_lf_ws = w.box_lf;
+  R.tr = Transpose{tr->col_ptr, tr->nz, tr->nz_face};
+  R.face_yw = b.face_yw;
+  R.face_x0 = b.face_x0;
+  R.nz_rz = b.nz_rz;
+  R.owner_grad = b.owner_grad;
+  R.vol_face = st_->vol_face;
+  R.vol_scale = st_->vol_scale;
+  R.scale_bar = scale_bar;
+  rc = reduce_moments(*opts, R, st);
+  if (rc) return rc;
+  CC_HIP(hipStreamSynchronize(st));
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
 }
 
 const char* cutcell_last_error(void) { return g_last_error.c_str(); }

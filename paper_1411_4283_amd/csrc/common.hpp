@@ -123,6 +123,41 @@ __device__ __forceinline__ void recentre(double* m, const double* delta) {
   if constexpr (D >= 3) shift_dir<D, Q, 2>(m, delta[2]);
 }
 
+// Transpose of the re-centring: a^T S(delta) = (S(delta)^T a)^T, used by the adjoint.
+// (S^T a)_q = sum_{p >= q} C(p,q) delta^(p-q) a_p, one direction at a time; lower degrees
+// first, so the entries with a larger exponent in the line are still unchanged when read.
+template <int D, int Q, int DIR>
+__device__ __forceinline__ void shift_dir_T(double* a, double delta) {
+  constexpr int M = kNMono<D, Q>;
+  double pw[Q + 1];
+  pw[0] = 1.0;
+  static_for<1, Q + 1>([&](auto K) { pw[K] = pw[K - 1] * delta; });
+  static_for<0, M>([&](auto IDX) {
+    constexpr int idx = IDX;
+    constexpr int qd = kMono<D, Q>.e[idx][DIR];
+    constexpr int deg = kMono<D, Q>.e[idx][0] + kMono<D, Q>.e[idx][1] + kMono<D, Q>.e[idx][2];
+    double acc = a[idx];
+    static_for<1, Q - deg + 1>([&](auto T) {        // c = qd + t, t >= 1
+      constexpr int t = T;
+      constexpr int c = qd + t;
+      constexpr int ea = (DIR == 0) ? c : kMono<D, Q>.e[idx][0];
+      constexpr int eb = (DIR == 1) ? c : kMono<D, Q>.e[idx][1];
+      constexpr int ec = (DIR == 2) ? c : kMono<D, Q>.e[idx][2];
+      constexpr int src = mono_index<D>(ea, eb, ec);
+      constexpr double coef = (double)binom(c, qd);
+      acc = __builtin_fma(coef * pw[t], a[src], acc);
+    });
+    a[idx] = acc;
+  });
+}
+
+template <int D, int Q>
+__device__ __forceinline__ void recentre_T(double* a, const double* delta) {
+  if constexpr (D >= 3) shift_dir_T<D, Q, 2>(a, delta[2]);
+  if constexpr (D >= 2) shift_dir_T<D, Q, 1>(a, delta[1]);
+  shift_dir_T<D, Q, 0>(a, delta[0]);
+}
+
 // ---- grid geometry -------------------------------------------------------------------
 struct GridDims {
   int D;

@@ -10,6 +10,20 @@ __global__ void k_fill_i32(int32_t* p, long long n, int32_t v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_fill_f64(double* p, long long n, double v) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// row counts of an existing CSR, for binning the faces again (the adjoint)
+__global__ void k_rows_per_face(long long n_face, const int64_t* __restrict__ row_ptr, int32_t* __restrict__ nrows) {
+  long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (f < n_face) {
+    const int64_t n = row_ptr[f + 1] - row_ptr[f];
+    nrows[f] = (n < 0 || n > (int64_t)kMaxRows) ? kMaxRows + 1 : (int32_t)n;
+  }
+}
+
 static inline unsigned blocks_for(long long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // lattice face lf (in the concatenated lattice) -> direction and coordinates
@@ -142,6 +156,28 @@ __global__ void k_enum_eb(GridDims g, int G, const GeomPtrs* __restrict__ geoms,
   fref[F] = (int32_t)e;
 }
 
+// one byte per cell for the neighbour search: bit 0 volume, bit 1 + 2d + s the grid face
+// on side s (0 low, 1 high) of direction d has alpha > 0, bit 7 the cell has an EB face
+__global__ void k_cellinfo(GridDims g, const int32_t* __restrict__ vol_id, const int32_t* __restrict__ eb_id,
+                           const int32_t* __restrict__ face_id, uint8_t* __restrict__ info) {
+  const int gi = blockIdx.y;
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long long o = (long long)gi * g.ncell + c;
+  unsigned v = vol_id[o] >= 0 ? 1u : 0u;
+  if (v) {
+    int x[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+    for (int d = 0; d < g.D; ++d)
+      for (int s = 0; s < 2; ++s) {
+        int j[3] = {x[0], x[1], x[2]};
+        j[d] += s;
+        if (face_id[(long long)gi * g.NF + lattice_index(g, d, j)] >= 0) v |= 1u << (1 + 2 * d + s);
+      }
+    if (eb_id[o] >= 0) v |= 0x80u;
+  }
+  info[o] = (uint8_t)v;
+}
+
 int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st) {
   const GridDims& g = w.dims;
   const int D = o.dim, Q = o.order;
@@ -160,6 +196,8 @@ int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st) {
                      w.excl, w.offs, w.vol_id, w.vol_cell, w.box_id, w.box_lf, w.face_id, w.fcode, w.fref);
   hipLaunchKernelGGL(k_enum_eb, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, w.G, w.geoms, w.counts, w.offs,
                      w.eb_id, w.fcode, w.fref);
+  hipLaunchKernelGGL(k_cellinfo, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, w.vol_id, w.eb_id, w.face_id,
+                     w.cellinfo);
   CC_HIP(hipGetLastError());
   return CUTCELL_OK;
 }
@@ -181,7 +219,8 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
                                                    const GeomPtrs* __restrict__ geoms, const int32_t* __restrict__ vol_id,
                                                    const int32_t* __restrict__ eb_id, const int32_t* __restrict__ face_id,
                                                    const int32_t* __restrict__ box_id, const int64_t* __restrict__ counts,
-                                                   const int64_t* __restrict__ offs, int32_t* nrows, int32_t* maxrows,
+                                                   const int64_t* __restrict__ offs, const uint8_t* __restrict__ cellinfo,
+                                                   int32_t* nrows,
                                                    const int64_t* __restrict__ row_ptr, int32_t* col) {
   using W = Win<D, R>;
   __shared__ int8_t dist[W::NW];
@@ -194,7 +233,6 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
 
   const int32_t* vid = vol_id + gi * g.ncell;
   const int32_t* eid = eb_id + gi * g.ncell;
-  const int32_t* fid = face_id + gi * g.NF;
   const int32_t* bid = box_id + gi * g.NF;
 
   // window origin and extents; the adjacent cells sit at normal index R (and R + 1)
@@ -218,16 +256,20 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
   }
   const int NW = ext[0] * ext[1] * ext[2];
 
-  // per-lane window cells: global cell, volume flag, open faces to in-window neighbours
+  // per-lane window cells: global cell, info byte (volume, open faces, EB); open bits
+  // are kept only toward neighbours inside the window and the box
+  const uint8_t* inf = cellinfo + (long long)gi * g.ncell;
   long long cell[W::K];
   bool isvol[W::K];
   unsigned open[W::K];
+  unsigned info[W::K];
   int wpos[W::K][3];
 #pragma unroll
   for (int k = 0; k < W::K; ++k) {
     const int w = lane + 64 * k;
     isvol[k] = false;
     open[k] = 0;
+    info[k] = 0;
     cell[k] = -1;
     if (w >= NW) continue;
     int wc[3] = {w % ext[0], (w / ext[0]) % ext[1], w / (ext[0] * ext[1])};
@@ -240,17 +282,14 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
     }
     if (!inbox) continue;
     cell[k] = cell_index(g, x);
-    isvol[k] = vid[cell[k]] >= 0;
-    if (!isvol[k]) continue;
+    info[k] = inf[cell[k]];
+    isvol[k] = info[k] & 1u;
     for (int ax = 0; ax < D; ++ax)
       for (int s = 0; s < 2; ++s) {
-        int wn = wc[ax] + (s ? 1 : -1);
-        if (wn < 0 || wn >= ext[ax]) continue;
-        int xn = x[ax] + (s ? 1 : -1);
-        if (xn < 0 || xn >= g.n[ax]) continue;
-        int j[3] = {x[0], x[1], x[2]};
-        j[ax] += s;
-        if (fid[lattice_index(g, ax, j)] >= 0) open[k] |= 1u << (2 * ax + s);
+        const int wn = wc[ax] + (s ? 1 : -1);
+        const int xn = x[ax] + (s ? 1 : -1);
+        if (wn >= 0 && wn < ext[ax] && xn >= 0 && xn < g.n[ax] && ((info[k] >> (1 + 2 * ax + s)) & 1u))
+          open[k] |= 1u << (2 * ax + s);
       }
   }
   // distances: 0 at the adjacent volumes, R + 1 ("far") elsewhere
@@ -302,24 +341,15 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
 #pragma unroll
     for (int k = 0; k < W::K; ++k) {
       if (!inS[k]) continue;
-      c += 1;
-      c += eid[cell[k]] >= 0;
-      int x[3];
-      long long cc = cell[k];
-      x[0] = (int)(cc % g.n[0]); x[1] = (int)((cc / g.n[0]) % g.n[1]); x[2] = (int)(cc / ((long long)g.n[0] * g.n[1]));
+      c += 1 + (int)(info[k] >> 7);
+      const long long cc = cell[k];
+      const int x[3] = {(int)(cc % g.n[0]), (int)((cc / g.n[0]) % g.n[1]), (int)(cc / ((long long)g.n[0] * g.n[1]))};
       for (int ax = 0; ax < D; ++ax)
-        for (int s = 0; s < 2; ++s) {
-          if (x[ax] != (s ? g.n[ax] - 1 : 0)) continue;
-          int j[3] = {x[0], x[1], x[2]};
-          j[ax] += s;
-          c += bid[lattice_index(g, ax, j)] >= 0;
-        }
+        for (int s = 0; s < 2; ++s)
+          if (x[ax] == (s ? g.n[ax] - 1 : 0) && ((info[k] >> (1 + 2 * ax + s)) & 1u)) c += 1;   // box face
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-    if (lane == 0) {
-      nrows[F] = c;
-      atomicMax(maxrows, c);
-    }
+    if (lane == 0) nrows[F] = c;
     return;
   }
   // fill in ascending Phi order: volumes, EB faces, box faces by (d, side)
@@ -366,19 +396,17 @@ static void launch_neighbours(const Work& w, long long n_face, const int64_t* ro
                               hipStream_t st) {
   if (fill)
     hipLaunchKernelGGL((k_neighbours<D, R, true>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
-                       w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.nrows,
-                       w.bins + 2 * kNBuckets, row_ptr, col);
+                       w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
+                       w.nrows, row_ptr, col);
   else
     hipLaunchKernelGGL((k_neighbours<D, R, false>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
-                       w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.nrows,
-                       w.bins + 2 * kNBuckets, row_ptr, col);
+                       w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
+                       w.nrows, row_ptr, col);
 }
 
 int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const int64_t* row_ptr, int32_t* col,
                    bool fill, hipStream_t st) {
   if (n_face <= 0) return CUTCELL_OK;
-  if (!fill)
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins + 2 * kNBuckets, 1LL, 0);
   const int D = o.dim, R = o.path_radius;
 #define CC_NB(DD, RR) \
   if (D == DD && R == RR) { launch_neighbours<DD, RR>(w, n_face, row_ptr, col, fill, st); }
@@ -433,12 +461,20 @@ int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, i
 // binning by row count: buckets of 16 rows (N <= 16, ..., <= 128) and one bucket for
 // faces with fewer rows than monomials; perm lists faces bucket by bucket
 
-__global__ void k_bin_count(long long n_face, int M, const int32_t* __restrict__ nrows, int32_t* bins) {
+// per-block histograms in LDS, one global atomic per bucket per block
+__global__ __launch_bounds__(256) void k_bin_count(long long n_face, int M, const int32_t* __restrict__ nrows,
+                                                   int32_t* bins) {
+  __shared__ int32_t h[kNBuckets];
+  if (threadIdx.x < kNBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
   long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (f >= n_face) return;
-  const int N = nrows[f];
-  const int b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
-  atomicAdd(&bins[b], 1);
+  if (f < n_face) {
+    const int N = nrows[f];
+    const int b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
+    atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNBuckets && h[threadIdx.x]) atomicAdd(&bins[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void k_bin_starts(int32_t* bins) {
@@ -450,13 +486,53 @@ __global__ void k_bin_starts(int32_t* bins) {
   }
 }
 
-__global__ void k_bin_scatter(long long n_face, int M, const int32_t* __restrict__ nrows, int32_t* bins,
-                              int32_t* perm) {
+// each block ranks its faces per bucket in LDS, then reserves one range per bucket
+__global__ __launch_bounds__(256) void k_bin_scatter(long long n_face, int M, const int32_t* __restrict__ nrows,
+                                                     int32_t* bins, int32_t* perm) {
+  __shared__ int32_t h[kNBuckets];
+  __shared__ int32_t base[kNBuckets];
+  if (threadIdx.x < kNBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
   long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (f >= n_face) return;
-  const int N = nrows[f];
-  const int b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
-  perm[atomicAdd(&bins[kNBuckets + b], 1)] = (int32_t)f;
+  int b = -1, r = 0;
+  if (f < n_face) {
+    const int N = nrows[f];
+    b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
+    r = atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNBuckets) base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&bins[kNBuckets + threadIdx.x], h[threadIdx.x]) : 0;
+  __syncthreads();
+  if (b >= 0) perm[base[b] + r] = (int32_t)f;
+}
+
+// largest row count (block reduction, one atomic per block)
+__global__ __launch_bounds__(256) void k_max_rows(long long n_face, const int32_t* __restrict__ nrows, int32_t* out) {
+  __shared__ int32_t sm[256];
+  long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  sm[threadIdx.x] = (f < n_face) ? nrows[f] : 0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, sm[0]);
+}
+
+int max_rows(const Work& w, long long n_face, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins + 2 * kNBuckets, 1LL, 0);
+  if (n_face > 0)
+    hipLaunchKernelGGL(k_max_rows, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, w.nrows,
+                       w.bins + 2 * kNBuckets);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+int rows_per_face(const Work& w, long long n_face, const int64_t* row_ptr, hipStream_t st) {
+  if (n_face > 0)
+    hipLaunchKernelGGL(k_rows_per_face, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, row_ptr, w.nrows);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
 }
 
 int bin_faces(const Work& w, long long n_face, int M, hipStream_t st) {

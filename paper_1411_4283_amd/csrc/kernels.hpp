@@ -30,6 +30,7 @@ struct Work {
   int32_t* box_id;      // [G][NF]     local box-face index or -1
   int32_t* box_lf;      // [G][nboxslot] lattice face of each local box face
   int32_t* vol_cell;    // [G][ncell]  cell of each local volume
+  uint8_t* cellinfo;    // [G][ncell]  volume / open-face / EB bits for the neighbour search
   int64_t* counts;      // [G][4]      n_vol, n_eb, n_box, n_gface
   int64_t* offs;        // [3][G+1]    phi_off, vol_off, face_off
   int32_t* fcode;       // [G*maxface] per global flux face
@@ -46,6 +47,34 @@ struct Work {
 
 size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w);
 
+// Outputs of the per-face stencil adjoint (k_stencil_backward) and their layout.
+// device copy of the per-geometry gradient pointers (layouts as the inputs)
+struct GradPtrs {
+  double* vol_mom;
+  double* face_mom[3];
+  double* eb_mom;
+  double* eb_nmom;
+};
+
+struct BackwardArgs {
+  const double* val_bar;        // [nnz]
+  double* face_yw;              // [n_face][2][M]   y and w
+  double* face_x0;              // [n_face][4]      x0 / h
+  double* nz_rz;                // [nnz][2]         (W r, W z) of each row
+  double* weight_bar;           // [nnz] or null
+  double* owner_grad;           // [n_face][4]      EB faces: d/d vol_mom[owner][0..D]; 0 otherwise
+  const GradPtrs* grads;        // [G]  the face-moment and EB normal-moment gradients are
+                                //      written here directly (Fbar)
+};
+
+// Transposed (CSC) structure of the stencils: the nonzeros of each Phi entry in
+// ascending CSR position, with the face each belongs to.
+struct Transpose {
+  const int64_t* col_ptr;   // [n_phi + 1]
+  const int32_t* nz;        // [nnz]
+  const int32_t* nz_face;   // [nnz]
+};
+
 // enumeration (Sec. 2.1): flags, maps, global face table, counts and offsets
 int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st);
 // neighbour rows (Sec. 2.4): count (fill = false) or write col[] (fill = true)
@@ -56,13 +85,48 @@ int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, i
                   double* vol_scale, hipStream_t st);
 // binning by row count and the stencil solves (Sec. 2.2.1)
 int bin_faces(const Work& w, long long n_face, int M, hipStream_t st);
+int max_rows(const Work& w, long long n_face, hipStream_t st);
 int solve_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count /* host */, long long n_face,
                    const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st);
+// Arguments of the per-Phi-entry sum of the rows' moment gradients.
+struct ReduceArgs {
+  GridDims g;
+  int G;
+  long long n_phi;
+  const int64_t* offs;        // [3][G+1] phi_off, vol_off, face_off
+  const int64_t* counts;      // [G][4]
+  const GeomPtrs* geoms;
+  const GradPtrs* grads;
+  const int32_t* vol_cell_ws;
+  const int32_t* box_lf_ws;
+  Transpose tr;
+  const double* face_yw;
+  const double* face_x0;
+  const double* nz_rz;
+  const double* owner_grad;
+  const int32_t* vol_face;    // [n_vol][2D+1]
+  const double* vol_scale;    // [n_vol]
+  const double* scale_bar;    // [n_vol] or null
+};
+
+int backward_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
+                      const int32_t* col, const BackwardArgs& bw, hipStream_t st);
+int rows_per_face(const Work& w, long long n_face, const int64_t* row_ptr, hipStream_t st);
+int reduce_moments(const cutcell_opts& o, const ReduceArgs& R, hipStream_t st);
+// transpose of the stencils and the apply adjoint
+size_t transpose_temp_bytes(long long nnz, long long n_phi);
+int build_transpose(long long n_face, long long n_phi, long long nnz, const int64_t* row_ptr, const int32_t* col,
+                    int64_t* col_ptr, int32_t* nz, int32_t* nz_face, char* ws, size_t ws_bytes, hipStream_t st);
+int apply_adjoint(int D, long long n_face, long long n_vol, long long n_phi, const int64_t* row_ptr,
+                  const int32_t* col, const double* val, const int32_t* vol_face, const double* vol_scale,
+                  const Transpose& tr, const double* phi, const double* flux, const double* lbar, double* phi_bar,
+                  double* val_bar, double* scale_bar, double* fbar, hipStream_t st);
 // operator apply (Sec. 2.2, Sec. 3.3)
 int apply_operator(int D, long long n_face, long long n_vol, const int64_t* row_ptr, const int32_t* col,
                    const double* val, const int32_t* vol_face, const double* vol_scale, const double* phi,
                    double* lphi, double* flux, double* flux_tmp, hipStream_t st);
 
 __global__ void k_fill_i32(int32_t* p, long long n, int32_t v);
+__global__ void k_fill_f64(double* p, long long n, double v);
 
 }  // namespace cutcell

@@ -18,6 +18,7 @@
 // Status: fewer rows than monomials, a pivot square root below 1e-7 times the largest after
 // equilibration (numerically rank deficient), or a non-finite entry flag the face.
 #include "kernels.hpp"
+#include "rows.hpp"
 
 namespace cutcell {
 
@@ -26,85 +27,22 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr double kRankTol = 1e-7;
 constexpr int kRefine = 2;
 
-template <int D, int Q>
-struct Dims {
-  static constexpr int M = binom(Q + D, D);
-  static constexpr int Mf = binom(Q + D - 1, D - 1);
-  static constexpr int M1 = binom(Q - 1 + D, D);
-  static constexpr int MT = (M + 15) / 16;   // 16-wide tiles covering M columns
-  static constexpr int MS = M | 1;           // odd LDS row stride (fewer bank conflicts)
-};
-
-// transverse face-monomial index of the D-variate monomial idx when its exponent in the
-// face direction dd is 0, else -1
-template <int D, int Q>
-__host__ __device__ constexpr int face_slot(int idx, int dd) {
-  const auto& T = kMono<D, Q>;
-  const int a = T.e[idx][0], b = T.e[idx][1], c = T.e[idx][2];
-  if (D == 2) {
-    if (dd == 0) return a == 0 ? mono_index<1>(b, 0, 0) : -1;
-    return b == 0 ? mono_index<1>(a, 0, 0) : -1;
-  }
-  if (dd == 0) return a == 0 ? mono_index<2>(b, c, 0) : -1;
-  if (dd == 1) return b == 0 ? mono_index<2>(a, c, 0) : -1;
-  return c == 0 ? mono_index<2>(a, b, 0) : -1;
-}
-
-// One row of A~ about x0 (in units of h: x0h = x0 / h), with its weight and centre.
+// One row of B = W A~ about x0 (in units of h: x0h = x0 / h), with its weight.
 // Returns false if the row holds a non-finite value.
 template <int D, int Q>
 __device__ __forceinline__ bool build_row(const GridDims& g, const GeomPtrs& gp, int64_t phi_local, int64_t n_vol,
                                           int64_t n_eb, const int32_t* vol_cell, const int32_t* box_lf,
                                           const double* x0h, double* m, double& w) {
-  constexpr int M = Dims<D, Q>::M, Mf = Dims<D, Q>::Mf;
-  double ctr[3] = {0, 0, 0};   // row centre / h
-  if (phi_local < n_vol + n_eb) {
-    int32_t c;
-    const double* src;
-    if (phi_local < n_vol) {
-      c = vol_cell[phi_local];
-      src = gp.vol_mom + (long long)c * M;
-    } else {
-      const int64_t e = phi_local - n_vol;
-      c = gp.eb_cell[e];
-      src = gp.eb_mom + e * M;
-    }
-    const int ci[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
-    for (int ax = 0; ax < D; ++ax) ctr[ax] = ci[ax] + 0.5;
-    static_for<0, M>([&](auto I) { m[I] = src[I]; });
-  } else {
-    const int32_t lf = box_lf[phi_local - n_vol - n_eb];
-    const int dd = (lf >= g.foff[1]) + (lf >= g.foff[2]);
-    const long long loc = lf - g.foff[dd];
-    const int m0 = g.n[0] + (dd == 0), m1 = g.n[1] + (dd == 1);
-    const int j[3] = {(int)(loc % m0), (int)((loc / m0) % m1), (int)(loc / ((long long)m0 * m1))};
-    for (int ax = 0; ax < D; ++ax) ctr[ax] = (ax == dd) ? (double)j[ax] : j[ax] + 0.5;
-    const double* src = gp.face_mom[dd] + loc * Mf;
-    auto embed = [&](auto DD) {
-      static_for<0, M>([&](auto I) {
-        constexpr int sl = face_slot<D, Q>(I, DD);
-        if constexpr (sl >= 0) m[I] = src[sl];
-        else m[I] = 0.0;
-      });
-    };
-    if (dd == 0) embed(std::integral_constant<int, 0>{});
-    else if (dd == 1) embed(std::integral_constant<int, 1>{});
-    else if constexpr (D == 3) embed(std::integral_constant<int, 2>{});
-  }
+  constexpr int M = Dims<D, Q>::M;
+  const RowSource rs = row_source<D, Q>(g, gp, phi_local, n_vol, n_eb, vol_cell, box_lf);
+  load_row_moments<D, Q>(rs, m);
   double delta[3] = {0, 0, 0};
   double d2 = 0;
   for (int ax = 0; ax < D; ++ax) {
-    delta[ax] = ctr[ax] - x0h[ax];
+    delta[ax] = rs.ctr[ax] - x0h[ax];
     d2 += delta[ax] * delta[ax];
   }
-  const double dist = sqrt(d2);
-  if (dist < 0.5) {
-    w = 1.0;
-  } else {
-    const double t = 2.0 * dist;
-    const double t2 = t * t;
-    w = 1.0 / (t2 * t2 * t);
-  }
+  w = row_weight(d2);
   const double mu0 = m[0];
   recentre<D, Q>(m, delta);
   const double sc = w / mu0;
@@ -116,55 +54,51 @@ __device__ __forceinline__ bool build_row(const GridDims& g, const GeomPtrs& gp,
   return finite;
 }
 
+// Shared memory of one face (one wave).
 template <int D, int Q, int NPAD>
-__global__ __launch_bounds__(64) void k_stencil(GridDims g, int G, double hscale, const int32_t* __restrict__ perm,
-                                               long long nbin, const int32_t* __restrict__ fcode,
-                                               const int32_t* __restrict__ fref, const GeomPtrs* __restrict__ geoms,
-                                               const int64_t* __restrict__ counts, const int64_t* __restrict__ offs,
-                                               const int32_t* __restrict__ vol_cell_ws,
-                                               const int32_t* __restrict__ box_lf_ws, const int64_t* __restrict__ row_ptr,
-                                               const int32_t* __restrict__ col, double* __restrict__ val,
-                                               int8_t* __restrict__ status, int32_t* flagged) {
-  using DM = Dims<D, Q>;
-  constexpr int M = DM::M, Mf = DM::Mf, M1 = DM::M1, MT = DM::MT, MS = DM::MS;
-  __shared__ double Bs[NPAD * MS];
-  __shared__ double Ls[M * MS];
-  __shared__ double vec[2][M + 1];
-  __shared__ double zs[NPAD];
-  __shared__ double wls[NPAD];
-  __shared__ double nus[D][M1];
+struct FaceSmem {
+  static constexpr int M = Dims<D, Q>::M, MS = Dims<D, Q>::MS, M1 = Dims<D, Q>::M1;
+  double Bs[NPAD * MS];      // rows of B = W A~
+  double Ls[M * MS];         // Gram matrix, then the pivot rows of the inversion
+  double vec[2][M + 1];      // F~ and a broadcast vector
+  double ys[M + 1];          // y = G^-1 F~
+  double zs[NPAD];           // z = B y
+  double wls[NPAD];          // W
+  double nus[D][M1];         // EB normal moments about x0
+};
 
-  const long long t = blockIdx.x;
-  if (t >= nbin) return;
-  const int lane = threadIdx.x;
-  const int32_t F = perm[t];
-  const int32_t code = fcode[F];
-  const int gi = code >> 4, kind = (code >> 2) & 3, dn = code & 3;
-  const int32_t ref = fref[F];
-  const GeomPtrs gp = geoms[gi];
-  const int64_t n_vol = counts[4 * gi + 0], n_eb = counts[4 * gi + 1];
-  const int64_t phi0 = offs[gi];
-  const int32_t* vol_cell = vol_cell_ws + (long long)gi * g.ncell;
-  const int32_t* box_lf = box_lf_ws + (long long)gi * g.nboxslot;
-  const int64_t rp = row_ptr[F];
-  const int N = (int)(row_ptr[F + 1] - rp);
+// Everything about the face that the row and flux computations need.
+struct FaceInfo {
+  int32_t F;
+  int gi, kind, dn;
+  int32_t ref;
+  int64_t n_vol, n_eb, phi0, rp;
+  int N;
+  double x0h[3];             // x0 / h
+  double off[3];             // EB faces: centroid offset from the cut cell's centre (/h)
+  int32_t owner_cell;        // EB faces: the cut cell
+};
 
-  // ---- x0 (in units of h) and the flux vector F~ ------------------------------------
-  double x0h[3] = {0, 0, 0};
-  int cown[3] = {0, 0, 0};
-  if (kind == 0) {
-    const long long loc = ref - g.foff[dn];
+// x0, the flux vector F~ (in sm.vec[0]) and, for EB faces, the re-centred normal moments
+template <int D, int Q, int NPAD>
+__device__ __forceinline__ void face_setup(const GridDims& g, const GeomPtrs& gp, FaceInfo& fi,
+                                           FaceSmem<D, Q, NPAD>& sm, int lane) {
+  constexpr int M = Dims<D, Q>::M, Mf = Dims<D, Q>::Mf, M1 = Dims<D, Q>::M1;
+  const int dn = fi.dn;
+  for (int ax = 0; ax < 3; ++ax) { fi.x0h[ax] = 0.0; fi.off[ax] = 0.0; }
+  fi.owner_cell = -1;
+  if (fi.kind == 0) {
+    const long long loc = fi.ref - g.foff[dn];
     const int m0 = g.n[0] + (dn == 0), m1 = g.n[1] + (dn == 1);
     const int j[3] = {(int)(loc % m0), (int)((loc / m0) % m1), (int)(loc / ((long long)m0 * m1))};
-    for (int ax = 0; ax < D; ++ax) x0h[ax] = (ax == dn) ? (double)j[ax] : j[ax] + 0.5;
+    for (int ax = 0; ax < D; ++ax) fi.x0h[ax] = (ax == dn) ? (double)j[ax] : j[ax] + 0.5;
     // F~_p = face moment of p - e_d when p_d = 1 (reference normal +e_d)
     const double* fm = gp.face_mom[dn] + loc * Mf;
     if (lane < M) {
       double fv = 0.0;
       constexpr auto& T = kMono<D, Q>;
-      // lanes index the monomial table at run time (constant-memory loads)
-      int e0 = T.e[lane][0], e1 = T.e[lane][1], e2 = T.e[lane][2];
-      int pd = (dn == 0) ? e0 : (dn == 1 ? e1 : e2);
+      const int e0 = T.e[lane][0], e1 = T.e[lane][1], e2 = T.e[lane][2];
+      const int pd = (dn == 0) ? e0 : (dn == 1 ? e1 : e2);
       if (pd == 1) {
         int s;
         if (D == 2) s = mono_index<1>(dn == 0 ? e1 : e0, 0, 0);
@@ -173,45 +107,60 @@ __global__ __launch_bounds__(64) void k_stencil(GridDims g, int G, double hscale
         else s = mono_index<2>(e0, e1, 0);
         fv = fm[s];
       }
-      vec[0][lane] = fv;
-    }
-  } else {
-    // EB face: x0 = centroid of the cut volume; the normal moments (about the cell
-    // centre) are re-centred to x0 by lanes 0..D-1, one component each
-    const int32_t c = gp.eb_cell[ref];
-    cown[0] = (int)(c % g.n[0]);
-    cown[1] = (int)((c / g.n[0]) % g.n[1]);
-    cown[2] = (int)(c / ((long long)g.n[0] * g.n[1]));
-    const double* vm = gp.vol_mom + (long long)c * M;
-    const double k0 = vm[0];
-    double off[3] = {0, 0, 0};
-    for (int ax = 0; ax < D; ++ax) {
-      off[ax] = vm[1 + ax] / k0;          // first moments: degree-1 monomials e_1..e_D
-      x0h[ax] = cown[ax] + 0.5 + off[ax];
-    }
-    if (lane < D) {
-      double nu[M1];
-      const double* src = gp.eb_nmom + ((long long)ref * D + lane) * M1;
-      static_for<0, M1>([&](auto I) { nu[I] = src[I]; });
-      double dl[3] = {-off[0], -off[1], -off[2]};   // (c - x0)/h
-      recentre<D, Q - 1>(nu, dl);
-      static_for<0, M1>([&](auto I) { nus[lane][I] = nu[I]; });
+      sm.vec[0][lane] = fv;
     }
     __syncthreads();
-    if (lane < M) {
-      constexpr auto& T = kMono<D, Q>;
-      double fv = 0.0;
-      for (int ax = 0; ax < D; ++ax) {
-        int e[3] = {T.e[lane][0], T.e[lane][1], T.e[lane][2]};
-        const int p = e[ax];
-        if (p > 0) {
-          e[ax] -= 1;
-          fv += p * nus[ax][mono_index<D>(e[0], e[1], e[2])];
-        }
-      }
-      vec[0][lane] = fv;
-    }
+    return;
   }
+  // EB face: x0 = centroid of the cut volume; the normal moments (about the cell centre)
+  // are re-centred to x0 by lanes 0..D-1, one component each
+  const int32_t c = gp.eb_cell[fi.ref];
+  fi.owner_cell = c;
+  const int cown[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+  const double* vm = gp.vol_mom + (long long)c * M;
+  const double k0 = vm[0];
+  for (int ax = 0; ax < D; ++ax) {
+    fi.off[ax] = vm[1 + ax] / k0;          // first moments: degree-1 monomials e_1..e_D
+    fi.x0h[ax] = cown[ax] + 0.5 + fi.off[ax];
+  }
+  if (lane < D) {
+    double nu[M1];
+    const double* src = gp.eb_nmom + ((long long)fi.ref * D + lane) * M1;
+    static_for<0, M1>([&](auto I) { nu[I] = src[I]; });
+    double dl[3] = {-fi.off[0], -fi.off[1], -fi.off[2]};   // (c - x0)/h
+    recentre<D, Q - 1>(nu, dl);
+    static_for<0, M1>([&](auto I) { sm.nus[lane][I] = nu[I]; });
+  }
+  __syncthreads();
+  if (lane < M) {
+    constexpr auto& T = kMono<D, Q>;
+    double fv = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+      int e[3] = {T.e[lane][0], T.e[lane][1], T.e[lane][2]};
+      const int p = e[ax];
+      if (p > 0) {
+        e[ax] -= 1;
+        fv += p * sm.nus[ax][mono_index<D>(e[0], e[1], e[2])];
+      }
+    }
+    sm.vec[0][lane] = fv;
+  }
+  __syncthreads();
+}
+
+// Rows, Gram matrix, inverse and the refined semi-normal solve of one face.  Leaves B, W,
+// z and y in shared memory and -G^^-1 (row `lane`) in a[], the column
+// equilibration in sdiag.  Returns the face status.
+template <int D, int Q, int NPAD>
+__device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
+                                            const int32_t* __restrict__ vol_cell, const int32_t* __restrict__ box_lf,
+                                            const int32_t* __restrict__ col, FaceSmem<D, Q, NPAD>& sm, int lane,
+                                            double* a, double& sdiag) {
+  using DM = Dims<D, Q>;
+  constexpr int M = DM::M, MT = DM::MT, MS = DM::MS;
+  double* Bs = sm.Bs;
+  double* Ls = sm.Ls;
+  const int N = fi.N;
 
   // ---- rows of B ----------------------------------------------------------------------
   bool finite = true;
@@ -220,51 +169,51 @@ __global__ __launch_bounds__(64) void k_stencil(GridDims g, int G, double hscale
     double m[M];
     double wr = 0.0;
     if (r < N) {
-      const int64_t loc = (int64_t)col[rp + r] - phi0;
-      finite = build_row<D, Q>(g, gp, loc, n_vol, n_eb, vol_cell, box_lf, x0h, m, wr) && finite;
+      const int64_t loc = (int64_t)col[fi.rp + r] - fi.phi0;
+      finite = build_row<D, Q>(g, gp, loc, fi.n_vol, fi.n_eb, vol_cell, box_lf, fi.x0h, m, wr) && finite;
     } else {
       static_for<0, M>([&](auto I) { m[I] = 0.0; });
     }
     static_for<0, M>([&](auto I) { Bs[r * MS + I] = m[I]; });
-    wls[r] = wr;
-    zs[r] = 0.0;
+    sm.wls[r] = wr;
+    sm.zs[r] = 0.0;
   }
   __syncthreads();
-  const bool allfinite = __all(finite) && __all(lane >= M || isfinite(vec[0][lane < M ? lane : 0]));
+  const bool allfinite = __all(finite) && __all(lane >= M || isfinite(sm.vec[0][lane < M ? lane : 0]));
 
   // ---- G = B^T B on the matrix cores ----------------------------------------------------
   dbl4 acc[MT][MT];
 #pragma unroll
-  for (int a = 0; a < MT; ++a)
+  for (int i = 0; i < MT; ++i)
 #pragma unroll
-    for (int b = 0; b < MT; ++b) acc[a][b] = dbl4{0, 0, 0, 0};
+    for (int j = 0; j < MT; ++j) acc[i][j] = dbl4{0, 0, 0, 0};
   const int lr = lane >> 4, lc = lane & 15;
-#pragma unroll 2
+#pragma unroll
   for (int k0 = 0; k0 < NPAD; k0 += 4) {
     double x[MT];
 #pragma unroll
-    for (int a = 0; a < MT; ++a) {
-      const int cidx = 16 * a + lc;
-      x[a] = (cidx < M) ? Bs[(k0 + lr) * MS + cidx] : 0.0;
+    for (int i = 0; i < MT; ++i) {
+      const int cidx = 16 * i + lc;
+      x[i] = (cidx < M) ? Bs[(k0 + lr) * MS + cidx] : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < MT; ++a)
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
-      for (int b = a; b < MT; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], x[b], acc[a][b], 0, 0, 0);
+      for (int j = i; j < MT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], x[j], acc[i][j], 0, 0, 0);
   }
-  // tile (a, b), register q holds G[16a + lane/16 + 4q][16b + lane%16] (the output layout
+  // tile (i, j), register q holds G[16i + lane/16 + 4q][16j + lane%16] (the output layout
   // of v_mfma_f64_16x16x4f64); each entry of the symmetric matrix is written once
-  // (i <= j) together with its mirror
+  // (r <= c) together with its mirror
 #pragma unroll
-  for (int a = 0; a < MT; ++a)
+  for (int i = 0; i < MT; ++i)
 #pragma unroll
-    for (int b = a; b < MT; ++b)
+    for (int j = i; j < MT; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = 16 * a + lr + 4 * q, j = 16 * b + lc;
-        if (i < M && j < M && i <= j) {
-          Ls[i * MS + j] = acc[a][b][q];
-          Ls[j * MS + i] = acc[a][b][q];
+        const int r = 16 * i + lr + 4 * q, c = 16 * j + lc;
+        if (r < M && c < M && r <= c) {
+          Ls[r * MS + c] = acc[i][j][q];
+          Ls[c * MS + r] = acc[i][j][q];
         }
       }
   __syncthreads();
@@ -275,13 +224,12 @@ __global__ __launch_bounds__(64) void k_stencil(GridDims g, int G, double hscale
   // which gives the rank test.  The pivot row (= column, by symmetry) goes through LDS.
   const bool act = lane < M;
   const int li = act ? lane : 0;         // clamped index for inactive lanes' LDS reads
-  const double sdiag = act ? 1.0 / sqrt(Ls[li * MS + li]) : 1.0;
-  if (act) vec[1][lane] = sdiag;
+  sdiag = act ? 1.0 / sqrt(Ls[li * MS + li]) : 1.0;
+  if (act) sm.vec[1][lane] = sdiag;
   __syncthreads();
-  double a[M];
-  static_for<0, M>([&](auto J) { a[J] = act ? Ls[li * MS + J] * sdiag * vec[1][J] : 0.0; });
+  static_for<0, M>([&](auto J) { a[J] = act ? Ls[li * MS + J] * sdiag * sm.vec[1][J] : 0.0; });
   __syncthreads();
-  double* prow = Ls;                     // the factored matrix is no longer needed in LDS
+  double* prow = Ls;                     // the Gram matrix is no longer needed in LDS
   double pmax = 0.0, pmin = 1e300;
   static_for<0, M>([&](auto K) {
     constexpr int k = K;
@@ -308,40 +256,302 @@ __global__ __launch_bounds__(64) void k_stencil(GridDims g, int G, double hscale
 
   // ---- semi-normal solve with refinement ----------------------------------------------------
   // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs)
-  if (act) vec[1][lane] = vec[0][lane] * sdiag;      // E F~
+  if (act) {
+    sm.vec[1][lane] = sm.vec[0][lane] * sdiag;      // E F~
+    sm.ys[lane] = 0.0;
+  }
   __syncthreads();
   for (int it = 0; it <= kRefine; ++it) {
     double y = 0.0;
-    static_for<0, M>([&](auto J) { y = fma(-a[J], vec[1][J], y); });
+    static_for<0, M>([&](auto J) { y = fma(-a[J], sm.vec[1][J], y); });
     __syncthreads();
-    if (act) vec[1][lane] = y * sdiag;
+    if (act) {
+      sm.vec[1][lane] = y * sdiag;
+      sm.ys[lane] += y * sdiag;
+    }
     __syncthreads();
     // z += B y
 #pragma unroll 1
     for (int r = lane; r < NPAD; r += 64) {
       double s = 0.0;
-#pragma unroll
-      for (int j = 0; j < M; ++j) s = fma(Bs[r * MS + j], vec[1][j], s);
-      zs[r] += s;
+      static_for<0, M>([&](auto J) { s = fma(Bs[r * MS + J], sm.vec[1][J], s); });
+      sm.zs[r] += s;
     }
     __syncthreads();
     if (it == kRefine) break;
-    // residual of B^T z = F~, equilibrated
+    // residual of B^T z = F~, equilibrated; four accumulators break the latency chain
     double res = 0.0;
     if (act) {
-      res = vec[0][lane];
-      for (int r = 0; r < N; ++r) res = fma(-Bs[r * MS + lane], zs[r], res);
+      double r0 = sm.vec[0][lane], r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      for (int r = 0; r < NPAD; r += 4) {
+        r0 = fma(-Bs[(r + 0) * MS + lane], sm.zs[r + 0], r0);
+        r1 = fma(-Bs[(r + 1) * MS + lane], sm.zs[r + 1], r1);
+        r2 = fma(-Bs[(r + 2) * MS + lane], sm.zs[r + 2], r2);
+        r3 = fma(-Bs[(r + 3) * MS + lane], sm.zs[r + 3], r3);
+      }
+      res = (r0 + r1) + (r2 + r3);
     }
     __syncthreads();
-    if (act) vec[1][lane] = res * sdiag;
+    if (act) sm.vec[1][lane] = res * sdiag;
     __syncthreads();
   }
+  return st;
+}
 
-  // ---- outputs ---------------------------------------------------------------------------
-  for (int r = lane; r < N; r += 64) val[rp + r] = (st == CUTCELL_STATUS_OK) ? hscale * wls[r] * zs[r] : 0.0;
+struct StencilArgs {
+  GridDims g;
+  int G;
+  double hscale;
+  const int32_t* perm;
+  long long nbin;
+  const int32_t* fcode;
+  const int32_t* fref;
+  const GeomPtrs* geoms;
+  const int64_t* counts;
+  const int64_t* offs;
+  const int32_t* vol_cell_ws;
+  const int32_t* box_lf_ws;
+  const int64_t* row_ptr;
+  const int32_t* col;
+};
+
+__device__ __forceinline__ FaceInfo face_info(const StencilArgs& A, long long t) {
+  FaceInfo fi;
+  fi.F = A.perm[t];
+  const int32_t code = A.fcode[fi.F];
+  fi.gi = code >> 4;
+  fi.kind = (code >> 2) & 3;
+  fi.dn = code & 3;
+  fi.ref = A.fref[fi.F];
+  fi.n_vol = A.counts[4 * fi.gi + 0];
+  fi.n_eb = A.counts[4 * fi.gi + 1];
+  fi.phi0 = A.offs[fi.gi];
+  fi.rp = A.row_ptr[fi.F];
+  fi.N = (int)(A.row_ptr[fi.F + 1] - fi.rp);
+  return fi;
+}
+
+template <int D, int Q, int NPAD>
+__global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restrict__ val, int8_t* __restrict__ status,
+                                               int32_t* flagged) {
+  constexpr int M = Dims<D, Q>::M;
+  __shared__ FaceSmem<D, Q, NPAD> sm;
+  const long long t = blockIdx.x;
+  if (t >= A.nbin) return;
+  const int lane = threadIdx.x;
+  FaceInfo fi = face_info(A, t);
+  const GeomPtrs gp = A.geoms[fi.gi];
+  face_setup<D, Q, NPAD>(A.g, gp, fi, sm, lane);
+  double a[M];
+  double sdiag;
+  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
+                                          A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a, sdiag);
+  for (int r = lane; r < fi.N; r += 64)
+    val[fi.rp + r] = (st == CUTCELL_STATUS_OK) ? A.hscale * sm.wls[r] * sm.zs[r] : 0.0;
   if (lane == 0) {
-    status[F] = (int8_t)st;
+    status[fi.F] = (int8_t)st;
     if (st != CUTCELL_STATUS_OK) atomicAdd(flagged, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Adjoint of the stencil of one face (the derivative of the solution of Sec. 2.2.1).
+// With s~ = W z, z = B y, y = G^-1 F~, G = B^T B and a given s~bar:
+//   zbar = W s~bar,  Wbar_i = s~bar_i z_i (through s~ = W z),
+//   w = G^-1 B^T zbar (a least-squares solve, refined like the forward), r = zbar - B w,
+//   Bbar = r y^T - z w^T,  Fbar = w,  Abar = W Bbar,  Wbar_i += Bbar_i . A~_i.
+// Bbar_i . B_i = r_i z_i - z_i (B w)_i needs no pass over the row.  The rows' moments
+// get S(delta_i)^T Abar_i / mu0 - e_0 (Abar_i . A~_i) / mu0; that sum over the faces a
+// row appears in is formed per Phi entry by k_moment_reduce from what this kernel keeps:
+// y and w of the face, x0, and (W r, W z) per row.  For an EB face x0 is the centroid of
+// the cut volume, so every row's delta and weight and the re-centred normal moments also
+// depend on that volume's moments 0..D; their gradient goes to owner_grad.
+
+template <int D, int Q, int NPAD>
+__global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, BackwardArgs B) {
+  using DM = Dims<D, Q>;
+  constexpr int M = DM::M, MS = DM::MS, Mf = DM::Mf, M1 = DM::M1;
+  __shared__ FaceSmem<D, Q, NPAD> sm;
+  __shared__ double zbar[NPAD];   // W s~bar, then the residual r = zbar - B w
+  __shared__ double bw[NPAD];     // B w
+  __shared__ double wv[M + 1];    // w
+  __shared__ double gdx[64][3];   // per-lane sums of dl/dx0 over the rows
+  const long long t = blockIdx.x;
+  if (t >= A.nbin) return;
+  const int lane = threadIdx.x;
+  FaceInfo fi = face_info(A, t);
+  const GeomPtrs gp = A.geoms[fi.gi];
+  face_setup<D, Q, NPAD>(A.g, gp, fi, sm, lane);
+  double a[M];
+  double sdiag;
+  const int32_t* vol_cell = A.vol_cell_ws + (long long)fi.gi * A.g.ncell;
+  const int32_t* box_lf = A.box_lf_ws + (long long)fi.gi * A.g.nboxslot;
+  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag);
+  const bool act = lane < M;
+  const double* Bs = sm.Bs;
+  const int N = fi.N;
+  double* yw = B.face_yw + (long long)fi.F * 2 * M;
+  double* og = B.owner_grad + (long long)fi.F * 4;
+  if (lane < 4) B.face_x0[(long long)fi.F * 4 + lane] = (lane < 3) ? fi.x0h[lane] : 0.0;
+  if (st != CUTCELL_STATUS_OK) {   // a flagged face has s = 0 whatever its inputs: no gradient
+    for (int r = lane; r < N; r += 64) {
+      B.nz_rz[2 * (fi.rp + r)] = 0.0;
+      B.nz_rz[2 * (fi.rp + r) + 1] = 0.0;
+      if (B.weight_bar) B.weight_bar[fi.rp + r] = 0.0;
+    }
+    if (act) { yw[lane] = 0.0; yw[M + lane] = 0.0; }
+    if (lane < 4) og[lane] = 0.0;
+    return;
+  }
+  // s~bar = h^(D-2) val_bar;  zbar = W s~bar;  the direct part of Wbar in gdx-free regs
+  for (int r = lane; r < NPAD; r += 64) {
+    const double sb = (r < N) ? A.hscale * B.val_bar[fi.rp + r] : 0.0;
+    zbar[r] = sm.wls[r] * sb;
+  }
+  if (act) wv[lane] = 0.0;
+  __syncthreads();
+  // w = G^-1 B^T zbar, refined:  w += G^-1 B^T (zbar - B w)
+  for (int it = 0; it <= kRefine; ++it) {
+    double res = 0.0;
+    if (act) {
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      for (int r = 0; r < NPAD; r += 4) {
+        double e0 = zbar[r + 0], e1 = zbar[r + 1], e2 = zbar[r + 2], e3 = zbar[r + 3];
+        if (it > 0) { e0 -= bw[r + 0]; e1 -= bw[r + 1]; e2 -= bw[r + 2]; e3 -= bw[r + 3]; }
+        r0 = fma(Bs[(r + 0) * MS + lane], e0, r0);
+        r1 = fma(Bs[(r + 1) * MS + lane], e1, r1);
+        r2 = fma(Bs[(r + 2) * MS + lane], e2, r2);
+        r3 = fma(Bs[(r + 3) * MS + lane], e3, r3);
+      }
+      res = (r0 + r1) + (r2 + r3);
+    }
+    __syncthreads();
+    if (act) sm.vec[1][lane] = res * sdiag;
+    __syncthreads();
+    double dw = 0.0;
+    static_for<0, M>([&](auto J) { dw = fma(-a[J], sm.vec[1][J], dw); });
+    if (act) wv[lane] += dw * sdiag;
+    __syncthreads();
+    for (int r = lane; r < NPAD; r += 64) {
+      double s = 0.0;
+      static_for<0, M>([&](auto J) { s = fma(Bs[r * MS + J], wv[J], s); });
+      bw[r] = s;
+    }
+    __syncthreads();
+  }
+  if (act) {
+    yw[lane] = sm.ys[lane];
+    yw[M + lane] = wv[lane];
+  }
+  // per row: r = zbar - B w;  Wbar;  (W r, W z) for the moment reduction;  EB x0 terms
+  double gx[3] = {0, 0, 0};
+  for (int r = lane; r < N; r += 64) {
+    const double W = sm.wls[r], zz = sm.zs[r];
+    const double rr = zbar[r] - bw[r];
+    const double sb = A.hscale * B.val_bar[fi.rp + r];
+    const double bdot = zz * (rr - bw[r]);            // Bbar_i . B_i
+    const double wtot = sb * zz + bdot / W;           // dl/dW_i
+    if (B.weight_bar) B.weight_bar[fi.rp + r] = wtot;
+    B.nz_rz[2 * (fi.rp + r)] = W * rr;
+    B.nz_rz[2 * (fi.rp + r) + 1] = W * zz;
+    if (fi.kind == 1) {
+      // delta_i = x_i/h - x0h: d B_ip / d delta_d = p_d B_i,p-e_d (weight fixed), and
+      // dW/d delta_d = -5 W delta_d / |delta|^2 outside half a cell
+      const RowSource rs = row_source<D, Q>(A.g, gp, (int64_t)A.col[fi.rp + r] - fi.phi0, fi.n_vol, fi.n_eb,
+                                            vol_cell, box_lf);
+      double dl[3] = {0, 0, 0}, d2 = 0.0;
+      for (int ax = 0; ax < D; ++ax) {
+        dl[ax] = rs.ctr[ax] - fi.x0h[ax];
+        d2 += dl[ax] * dl[ax];
+      }
+      double gd[3] = {0, 0, 0};
+      static_for<0, M>([&](auto P) {
+        constexpr int p = P;
+        const double bb = rr * sm.ys[p] - zz * wv[p];   // Bbar_ip
+        static_for<0, D>([&](auto AX) {
+          constexpr int ax = AX;
+          constexpr int pd = kMono<D, Q>.e[p][ax];
+          if constexpr (pd > 0) {
+            constexpr int q = mono_index<D>(kMono<D, Q>.e[p][0] - (ax == 0), kMono<D, Q>.e[p][1] - (ax == 1),
+                                            kMono<D, Q>.e[p][2] - (ax == 2));
+            gd[ax] = fma(bb * pd, Bs[r * MS + q], gd[ax]);
+          }
+        });
+      });
+      if (sqrt(d2) >= 0.5)
+        for (int ax = 0; ax < D; ++ax) gd[ax] += wtot * (-5.0 * W * dl[ax] / d2);
+      for (int ax = 0; ax < D; ++ax) gx[ax] -= gd[ax];   // d delta / d x0h = -1
+    }
+  }
+  // flux-vector gradient Fbar = w
+  if (fi.kind == 0) {
+    if (lane < 4) og[lane] = 0.0;
+    if (act) {
+      constexpr auto& T = kMono<D, Q>;
+      const int dn = fi.dn;
+      const int e0 = T.e[lane][0], e1 = T.e[lane][1], e2 = T.e[lane][2];
+      const int pd = (dn == 0) ? e0 : (dn == 1 ? e1 : e2);
+      if (pd == 1) {
+        int s;
+        if (D == 2) s = mono_index<1>(dn == 0 ? e1 : e0, 0, 0);
+        else if (dn == 0) s = mono_index<2>(e1, e2, 0);
+        else if (dn == 1) s = mono_index<2>(e0, e2, 0);
+        else s = mono_index<2>(e0, e1, 0);
+        B.grads[fi.gi].face_mom[dn][(fi.ref - A.g.foff[dn]) * Mf + s] = wv[lane];
+      }
+    }
+    return;
+  }
+  // EB face: F~_p = sum_d p_d nu'_{d, p - e_d} with nu' the normal moments re-centred by
+  // delta0 = (c - x0)/h:  nu'bar_{d,q} = (q_d + 1) w_{q + e_d},  nubar = S(delta0)^T nu'bar,
+  // and d nu'_{d,q} / d delta0_k = q_k nu'_{d, q - e_k}
+  for (int ax = 0; ax < 3; ++ax) gdx[lane][ax] = gx[ax];
+  __syncthreads();
+  if (lane < D) {
+    double nb[M1];
+    double g0[3] = {0, 0, 0};
+    static_for<0, M1>([&](auto I) {
+      constexpr int i = I;
+      constexpr int q0 = kMono<D, Q - 1>.e[i][0], q1 = kMono<D, Q - 1>.e[i][1], q2 = kMono<D, Q - 1>.e[i][2];
+      const int qd = (lane == 0) ? q0 : (lane == 1 ? q1 : q2);
+      const int up = mono_index<D>(q0 + (lane == 0), q1 + (lane == 1), q2 + (lane == 2));
+      nb[i] = (qd + 1) * wv[up];
+    });
+    static_for<0, M1>([&](auto I) {
+      constexpr int i = I;
+      static_for<0, D>([&](auto K) {
+        constexpr int k = K;
+        constexpr int qk = kMono<D, Q - 1>.e[i][k];
+        if constexpr (qk > 0) {
+          constexpr int src = mono_index<D>(kMono<D, Q - 1>.e[i][0] - (k == 0), kMono<D, Q - 1>.e[i][1] - (k == 1),
+                                            kMono<D, Q - 1>.e[i][2] - (k == 2));
+          g0[k] = fma(nb[i] * qk, sm.nus[lane][src], g0[k]);
+        }
+      });
+    });
+    double d0[3] = {-fi.off[0], -fi.off[1], -fi.off[2]};
+    recentre_T<D, Q - 1>(nb, d0);
+    double* dst = B.grads[fi.gi].eb_nmom + ((long long)fi.ref * D + lane) * M1;
+    static_for<0, M1>([&](auto I) { dst[I] = nb[I]; });
+    for (int k = 0; k < 3; ++k) sm.vec[1][lane * 3 + k] = g0[k];   // dl/d delta0 from component `lane`
+  }
+  __syncthreads();
+  if (lane == 0) {
+    // dl/dx0h = sum over rows (gdx) - dl/d delta0;  x0h_d = centre_d + m^{e_d} / m^0
+    double gxh[3] = {0, 0, 0};
+    for (int l = 0; l < 64; ++l)
+      for (int ax = 0; ax < D; ++ax) gxh[ax] += gdx[l][ax];
+    for (int c = 0; c < D; ++c)
+      for (int k = 0; k < D; ++k) gxh[k] -= sm.vec[1][c * 3 + k];
+    const double* vm = gp.vol_mom + (long long)fi.owner_cell * M;
+    const double m0 = vm[0];
+    double g0 = 0.0;
+    for (int ax = 0; ax < D; ++ax) {
+      og[1 + ax] = gxh[ax] / m0;
+      g0 -= gxh[ax] * vm[1 + ax] / (m0 * m0);
+    }
+    og[0] = g0;
+    for (int ax = D; ax < 3; ++ax) og[1 + ax] = 0.0;
   }
 }
 
@@ -356,18 +566,58 @@ __global__ void k_insufficient(const int32_t* __restrict__ perm, long long n, co
   atomicAdd(flagged, 1);
 }
 
+static StencilArgs stencil_args(const Work& w, double hscale, const int32_t* perm, long long nbin,
+                                const int64_t* row_ptr, const int32_t* col) {
+  StencilArgs A;
+  A.g = w.dims;
+  A.G = w.G;
+  A.hscale = hscale;
+  A.perm = perm;
+  A.nbin = nbin;
+  A.fcode = w.fcode;
+  A.fref = w.fref;
+  A.geoms = w.geoms;
+  A.counts = w.counts;
+  A.offs = w.offs;
+  A.vol_cell_ws = w.vol_cell;
+  A.box_lf_ws = w.box_lf;
+  A.row_ptr = row_ptr;
+  A.col = col;
+  return A;
+}
+
+// faces with fewer rows than monomials carry no gradient
+__global__ void k_insufficient_backward(const int32_t* __restrict__ perm, long long n,
+                                        const int64_t* __restrict__ row_ptr, int M, BackwardArgs B) {
+  long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int32_t F = perm[t];
+  for (int64_t j = row_ptr[F]; j < row_ptr[F + 1]; ++j) {
+    B.nz_rz[2 * j] = 0.0;
+    B.nz_rz[2 * j + 1] = 0.0;
+    if (B.weight_bar) B.weight_bar[j] = 0.0;
+  }
+  for (int p = 0; p < 2 * M; ++p) B.face_yw[(long long)F * 2 * M + p] = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    B.owner_grad[(long long)F * 4 + k] = 0.0;
+    B.face_x0[(long long)F * 4 + k] = 0.0;
+  }
+}
+
 template <int D, int Q, int NPAD>
 static void launch_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, const int64_t* row_ptr,
-                       const int32_t* col, double* val, int8_t* status, hipStream_t st) {
+                       const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw) {
   if (nbin <= 0) return;
-  hipLaunchKernelGGL((k_stencil<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, w.dims, w.G, hscale, perm, nbin,
-                     w.fcode, w.fref, w.geoms, w.counts, w.offs, w.vol_cell, w.box_lf, row_ptr, col, val, status,
-                     w.flagged);
+  const StencilArgs A = stencil_args(w, hscale, perm, nbin, row_ptr, col);
+  if (bw)
+    hipLaunchKernelGGL((k_stencil_backward<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, A, *bw);
+  else
+    hipLaunchKernelGGL((k_stencil<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, A, val, status, w.flagged);
 }
 
 template <int D, int Q>
 static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count, const int64_t* row_ptr,
-                         const int32_t* col, double* val, int8_t* status, hipStream_t st) {
+                         const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw) {
   constexpr int M = binom(Q + D, D);
   long long start = 0;
   for (int b = 0; b < kMaxBins; ++b) {
@@ -378,34 +628,47 @@ static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count,
     const int npad = kBinRows * (b + 1);
     if (npad < M) return fail(CUTCELL_E_INVALID_ARG, "internal: face with N >= M in a bin narrower than M");
     switch (npad) {
-      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
-      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st); break;
+      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
     }
   }
   const long long ninsuf = bin_count[kMaxBins];
-  if (ninsuf > 0)
+  if (ninsuf > 0 && bw)
+    hipLaunchKernelGGL(k_insufficient_backward, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st,
+                       w.perm + start, ninsuf, row_ptr, (int)M, *bw);
+  else if (ninsuf > 0)
     hipLaunchKernelGGL(k_insufficient, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st, w.perm + start,
                        ninsuf, row_ptr, val, status, w.flagged);
   CC_HIP(hipGetLastError());
   return CUTCELL_OK;
 }
 
+static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
+                    const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw) {
+  double hscale = 1.0;
+  for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
+  if (o.dim == 2 && o.order == 2) return dispatch_bins<2, 2>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
+  if (o.dim == 2 && o.order == 4) return dispatch_bins<2, 4>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
+  if (o.dim == 3 && o.order == 2) return dispatch_bins<3, 2>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
+  if (o.dim == 3 && o.order == 4) return dispatch_bins<3, 4>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
+  return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");
+}
+
 int solve_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, long long n_face,
                    const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st) {
   (void)n_face;
-  double hscale = 1.0;
-  for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
-  if (o.dim == 2 && o.order == 2) return dispatch_bins<2, 2>(w, hscale, bin_count, row_ptr, col, val, status, st);
-  if (o.dim == 2 && o.order == 4) return dispatch_bins<2, 4>(w, hscale, bin_count, row_ptr, col, val, status, st);
-  if (o.dim == 3 && o.order == 2) return dispatch_bins<3, 2>(w, hscale, bin_count, row_ptr, col, val, status, st);
-  if (o.dim == 3 && o.order == 4) return dispatch_bins<3, 4>(w, hscale, bin_count, row_ptr, col, val, status, st);
-  return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");
+  return run_bins(w, o, bin_count, row_ptr, col, val, status, st, nullptr);
+}
+
+int backward_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
+                      const int32_t* col, const BackwardArgs& bw, hipStream_t st) {
+  return run_bins(w, o, bin_count, row_ptr, col, nullptr, nullptr, st, &bw);
 }
 
 }  // namespace cutcell

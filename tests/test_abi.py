@@ -27,7 +27,8 @@ def lib():
 def test_header_declares_the_entry_points():
     names = _declared()
     for n in ("cutcell_query", "cutcell_build_stencils", "cutcell_apply", "cutcell_workspace_bytes",
-              "cutcell_last_error", "cutcell_abi_version"):
+              "cutcell_last_error", "cutcell_abi_version", "cutcell_stencils_backward", "cutcell_apply_adjoint",
+              "cutcell_build_transpose", "cutcell_transpose_workspace_bytes", "cutcell_backward_workspace_bytes"):
         assert n in names
 
 
@@ -38,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 1
+    assert lib.cutcell_abi_version() == 2
 
 
 def _opts(**kw):

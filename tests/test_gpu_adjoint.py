@@ -1,0 +1,213 @@
+"""GPU parity of the adjoints (cutcell_apply_adjoint, cutcell_stencils_backward and the
+autograd wrappers) against the oracle's adjoints, through the C ABI.
+
+Bars (derived in the design notes; written in each test):
+  * apply adjoint: per entry |d| <= 1e-12 * (sum of the magnitudes of the terms);
+  * stencil gradients: per input array, max|g_gpu - g_orc| <= 1e-9 * max|g_orc|.  Each face
+    contributes a bilinear form in (y, w, r, z), each of which both sides get from a
+    refined or backward-stable solve with relative error <= ~cond(W A~) * eps; the faces'
+    condition numbers stay below 1e6 here, so per-face errors are <= ~1e-10 relative and
+    the sums over rows and faces add no cancellation beyond the largest term.
+Faces outside the compared subset get val_bar = 0 (their gradient is then zero on both
+sides), which keeps the oracle's per-face autograd within seconds.
+"""
+
+import numpy as np
+import pytest
+
+import cutgeom as cg
+import oracle
+
+torch = pytest.importorskip("torch")
+import paper_1411_4283_amd as cc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+GRAD_TOL = 1e-9
+
+
+def _say(msg):
+    print(f"[gpu-adjoint] {msg}", flush=True)
+
+
+CASES = {
+    "circle16_q2": (cg.ball_outside((0.5, 0.5), 0.25), 16, 2, 2, None),
+    "circle16_q4": (cg.ball_outside((0.5, 0.5), 0.25), 16, 4, 3, 160),
+    "sphere10_q4": (cg.ball_outside((0.5, 0.5, 0.5), 0.3), 10, 4, 3, 90),
+    "sphere8_q2": (cg.ball_outside((0.5, 0.5, 0.5), 0.3), 8, 2, 2, 120),
+}
+
+
+def _setup(name):
+    """GPU build plus the oracle's enumeration and neighbour rows (its stencils only where
+    a test needs them)."""
+    shape, n, Q, R, nsub = CASES[name]
+    g = cg.make_geometry(shape, n, Q)
+    en = oracle.enumerate_geometry(g)
+    nbr = [oracle.neighbours(en, f, R) for f in range(en.n_face)]
+    rp = np.zeros(en.n_face + 1, np.int64)
+    rp[1:] = np.cumsum([len(x) for x in nbr])
+    col = np.concatenate(nbr).astype(np.int32)
+    dg = cc.DeviceGeometry.from_host(g, DEV)
+    b = cc.Builder(dg, R)
+    st = b.build()
+    torch.cuda.synchronize()
+    assert np.array_equal(st.row_ptr.cpu().numpy(), rp)
+    assert np.array_equal(st.col.cpu().numpy()[: len(col)], col)
+    val = st.val.cpu().numpy()[: len(col)]
+    return g, en, rp, col, val, R, dg, b, st, nsub
+
+
+def _face_subset(en, nsub, seed):
+    """nsub faces: every EB face and grid face of a few cut cells, plus random others."""
+    if nsub is None:
+        return np.arange(en.n_face)
+    rng = np.random.default_rng(seed)
+    eb_faces = np.flatnonzero(en.face_kind == oracle.stencils.KIND_EB)
+    owners = set(int(en.face_lo[f]) for f in rng.choice(eb_faces, 3, replace=False))
+    near = [f for f in range(en.n_face) if int(en.face_lo[f]) in owners or int(en.face_hi[f]) in owners]
+    box = np.flatnonzero((en.face_lo < 0) | (en.face_hi < 0))
+    extra = rng.choice(en.n_face, nsub, replace=False)
+    sel = np.unique(np.concatenate([near, rng.choice(box, 6, replace=False), rng.choice(eb_faces, 6, replace=False),
+                                    extra]))
+    return sel
+
+
+def _val_bar(rp, faces, nnz, seed):
+    vb = np.zeros(nnz)
+    rng = np.random.default_rng(seed)
+    for f in faces:
+        vb[rp[f]:rp[f + 1]] = rng.standard_normal(rp[f + 1] - rp[f])
+    return vb
+
+
+def _cmp(name, got, ref, tol=GRAD_TOL):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max()
+    _say(f"{name}: max|ref| {scale:.3e} max err {err:.3e} rel {err / max(scale, 1e-300):.3e}")
+    assert err <= tol * scale + 1e-300, (name, err, scale)
+
+
+@pytest.mark.parametrize("name", ["circle16_q4", "sphere10_q4"])
+def test_apply_adjoint_matches_oracle(name):
+    g, en, rp, col, valg, R, dg, b, st, _ = _setup(name)
+    _say(f"apply adjoint {name}")
+    rng = np.random.default_rng(5)
+    phi = rng.standard_normal(en.n_phi)
+    lbar = rng.standard_normal(en.n_vol)
+    phi_t = torch.from_numpy(phi).to(DEV)
+    lphi, flux = cc.apply(st, phi_t)
+    phi_bar, val_bar, scale_bar, flux_bar = cc.apply_adjoint(st, torch.from_numpy(lbar).to(DEV), phi=phi_t,
+                                                             flux=flux)
+    torch.cuda.synchronize()
+    pb_o, vb_o, kb_o = oracle.apply_adjoint(g, en, rp, col, valg, phi, lbar)
+    # phi_bar: sums over the column's nonzeros of val * flux_bar
+    scale = 1.0 / (g.vol_mom[en.vol_cell, 0] * en.h**en.D)
+    c = np.zeros(en.n_face)
+    for side, sgn in ((en.face_lo, 1.0), (en.face_hi, -1.0)):
+        m = side >= 0
+        np.add.at(c, np.flatnonzero(m), sgn * lbar[side[m]] * scale[side[m]])
+    bound = np.zeros(en.n_phi)
+    np.add.at(bound, col, np.abs(valg * c[np.repeat(np.arange(en.n_face), np.diff(rp))]))
+    assert np.all(np.abs(phi_bar.cpu().numpy() - pb_o) <= 1e-12 * bound + 1e-300)
+    assert np.all(np.abs(val_bar.cpu().numpy() - vb_o) <= 1e-12 * np.abs(vb_o) + 1e-300)
+    # scale_bar -> kappa_bar = -scale_bar * scale / kappa
+    kap = g.vol_mom[en.vol_cell, 0]
+    kb_g = -scale_bar.cpu().numpy() * st.vol_scale.cpu().numpy()[: en.n_vol] / kap
+    assert np.all(np.abs(kb_g - kb_o) <= 1e-12 * np.abs(kb_o) + 1e-14 * np.abs(kb_o).max())
+    # transpose identity on the device results
+    lhs = float(torch.dot(torch.from_numpy(lbar).to(DEV), lphi))
+    rhs = float(torch.dot(phi_bar, phi_t))
+    assert abs(lhs - rhs) <= 1e-12 * float(torch.dot(torch.from_numpy(np.abs(lbar)).to(DEV), lphi.abs()))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stencil_gradients_match_oracle(name):
+    g, en, rp, col, val, R, dg, b, st, nsub = _setup(name)
+    faces = _face_subset(en, nsub, 11)
+    _say(f"stencils backward {name}: {len(faces)} of {en.n_face} faces")
+    vb = _val_bar(rp, faces, len(col), 12)
+    grads, wb = b.backward(st, torch.from_numpy(vb).to(DEV), weight_bar=True)
+    torch.cuda.synchronize()
+    G = oracle.stencils_backward(g, en, R, rp, vb, faces=faces)
+    gg = grads[0]
+    _cmp("vol_mom", gg["vol_mom"].cpu().numpy(), G["vol_mom"])
+    for d in range(g.D):
+        _cmp(f"face_mom[{d}]", gg["face_mom"][d].cpu().numpy(), G["face_mom"][d])
+    _cmp("eb_mom", gg["eb_mom"].cpu().numpy(), G["eb_mom"])
+    _cmp("eb_nmom", gg["eb_nmom"].cpu().numpy(), G["eb_nmom"])
+    _cmp("weight", wb.cpu().numpy(), G["weight"])
+
+
+def test_stencil_backward_is_deterministic():
+    g, en, rp, col, val, R, dg, b, st, _ = _setup("circle16_q4")
+    vb = torch.from_numpy(np.random.default_rng(3).standard_normal(len(col))).to(DEV)
+    g1, w1 = b.backward(st, vb, weight_bar=True)
+    g2, w2 = b.backward(st, vb, weight_bar=True)
+    torch.cuda.synchronize()
+    assert torch.equal(g1[0]["vol_mom"], g2[0]["vol_mom"])
+    assert torch.equal(g1[0]["eb_nmom"], g2[0]["eb_nmom"])
+    assert all(torch.equal(a, c) for a, c in zip(g1[0]["face_mom"], g2[0]["face_mom"]))
+    assert torch.equal(w1, w2)
+
+
+def test_batch_backward_equals_separate():
+    shapes = [cg.ball_outside((0.5, 0.5), 0.25), cg.ball_outside((0.47, 0.52), 0.27)]
+    geoms = [cg.make_geometry(s, 16, 4) for s in shapes]
+    dgs = [cc.DeviceGeometry.from_host(h, DEV) for h in geoms]
+    bb = cc.Builder(dgs, 3)
+    st = bb.build()
+    nnz = st.sizes.nnz
+    vb = torch.from_numpy(np.random.default_rng(9).standard_normal(nnz)).to(DEV)
+    gb, _ = bb.backward(st, vb)
+    off = 0
+    for i, dg in enumerate(dgs):
+        b1 = cc.Builder(dg, 3)
+        s1 = b1.build()
+        n1 = s1.sizes.nnz
+        g1, _ = b1.backward(s1, vb[off: off + n1].contiguous())
+        off += n1
+        assert torch.equal(g1[0]["vol_mom"], gb[i]["vol_mom"])
+        assert torch.equal(g1[0]["eb_mom"], gb[i]["eb_mom"])
+        assert all(torch.equal(a, c) for a, c in zip(g1[0]["face_mom"], gb[i]["face_mom"]))
+    assert off == nnz
+
+
+def test_autograd_loss_gradient_matches_oracle():
+    """l = sum over cut volumes of (L(Phi) - f)^2 with Phi the exact solution's averages:
+    torch.autograd through CutCellOperator vs the oracle's apply adjoint chained into its
+    stencil adjoint (including d(1/kappa)/dkappa)."""
+    shape = cg.ball_outside((0.5, 0.5), 0.25)
+    g = cg.make_geometry(shape, 16, 2)
+    R = 2
+    en, rp, col, val, status = oracle.build(g, R)
+    rng = np.random.default_rng(21)
+    phi = rng.standard_normal(en.n_phi)
+    f = rng.standard_normal(en.n_vol)
+    cut = np.isin(en.vol_cell, g.eb_cell).astype(np.float64)
+    dg = cc.DeviceGeometry.from_host(g, DEV)
+    for t in [dg.vol_mom, *dg.face_mom, dg.eb_mom, dg.eb_nmom]:
+        t.requires_grad_(True)
+    op = cc.CutCellOperator(dg, R)
+    phi_t = torch.from_numpy(phi).to(DEV).requires_grad_(True)
+    L = op(phi_t)
+    loss = torch.sum(torch.from_numpy(cut).to(DEV) * (L - torch.from_numpy(f).to(DEV)) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    # oracle chain
+    _, L_o = oracle.apply(g, en, rp, col, val, phi)
+    lbar = 2 * cut * (L_o - f)
+    pb_o, vb_o, kb_o = oracle.apply_adjoint(g, en, rp, col, val, phi, lbar)
+    G = oracle.stencils_backward(g, en, R, rp, vb_o, weights=False)
+    vol_o = G["vol_mom"].copy()
+    np.add.at(vol_o[:, 0], en.vol_cell, kb_o)
+    _cmp("phi", phi_t.grad.cpu().numpy(), pb_o)
+    _cmp("vol_mom", dg.vol_mom.grad.cpu().numpy(), vol_o)
+    for d in range(2):
+        _cmp(f"face_mom[{d}]", dg.face_mom[d].grad.cpu().numpy(), G["face_mom"][d])
+    _cmp("eb_mom", dg.eb_mom.grad.cpu().numpy(), G["eb_mom"])
+    _cmp("eb_nmom", dg.eb_nmom.grad.cpu().numpy(), G["eb_nmom"])
