@@ -221,33 +221,27 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   // ---- equilibrate to unit diagonal and invert: lane i holds row i ----------------------------
   // Symmetric Gauss-Jordan sweeps over the pivots k = 0..M-1 turn G^ into -G^-1 in place;
   // the pivot of step k is the k-th Schur complement pivot (L_kk^2 of the Cholesky factor),
-  // which gives the rank test.  The pivot row (= column, by symmetry) goes through LDS.
+  // which gives the rank test.  Lane k's row is the pivot row (= column, by symmetry); the
+  // other lanes read it with v_readlane, so a sweep step touches neither LDS nor a barrier.
   const bool act = lane < M;
   const int li = act ? lane : 0;         // clamped index for inactive lanes' LDS reads
   sdiag = act ? 1.0 / sqrt(Ls[li * MS + li]) : 1.0;
-  if (act) sm.vec[1][lane] = sdiag;
-  __syncthreads();
-  static_for<0, M>([&](auto J) { a[J] = act ? Ls[li * MS + J] * sdiag * sm.vec[1][J] : 0.0; });
-  __syncthreads();
-  double* prow = Ls;                     // the Gram matrix is no longer needed in LDS
+  static_for<0, M>([&](auto J) { a[J] = act ? Ls[li * MS + J] * sdiag * readlane_f64(sdiag, J) : 0.0; });
   double pmax = 0.0, pmin = 1e300;
   static_for<0, M>([&](auto K) {
     constexpr int k = K;
-    if (lane == k) static_for<0, M>([&](auto J) { prow[J] = a[J]; });
-    __syncthreads();
-    const double d = prow[k];
+    const double d = readlane_f64(a[k], k);
     const double sq = sqrt(d > 0.0 ? d : 0.0);
     pmax = fmax(pmax, sq);
     pmin = fmin(pmin, sq);
     const double rd = 1.0 / d;
-    const double u = (lane == k) ? d - 1.0 : prow[li];   // a_ik = a_ki
+    const double u = (lane == k) ? d - 1.0 : a[k];      // a_ik (before this step)
     static_for<0, M>([&](auto J) {
       constexpr int j = J;
-      const double wj = (j == k) ? 1.0 - rd : prow[j] * rd;
+      const double wj = (j == k) ? 1.0 - rd : readlane_f64(a[j], k) * rd;
       a[j] = fma(-u, wj, a[j]);
     });
     if (lane == k) a[k] = -rd;
-    __syncthreads();
   });
   const bool rankok = (pmin > kRankTol * pmax) && (pmax > 0.0);
   int st = CUTCELL_STATUS_OK;
@@ -255,34 +249,42 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   else if (!rankok) st = CUTCELL_STATUS_RANK_DEFICIENT;
 
   // ---- semi-normal solve with refinement ----------------------------------------------------
-  // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs)
-  if (act) {
-    sm.vec[1][lane] = sm.vec[0][lane] * sdiag;      // E F~
-    sm.ys[lane] = 0.0;
-  }
-  __syncthreads();
+  // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs).  Lane p holds
+  // component p of F~, rhs and y; lane r holds z of its rows r, r + 64.
+  constexpr int NR = (NPAD + 63) / 64;
+  const double fv = act ? sm.vec[0][lane] : 0.0;
+  double rhs = fv * sdiag;
+  double ysum = 0.0;
+  double zr[NR];
+  static_for<0, NR>([&](auto R) { zr[R] = 0.0; });
   for (int it = 0; it <= kRefine; ++it) {
-    double y = 0.0;
-    static_for<0, M>([&](auto J) { y = fma(-a[J], sm.vec[1][J], y); });
-    __syncthreads();
-    if (act) {
-      sm.vec[1][lane] = y * sdiag;
-      sm.ys[lane] += y * sdiag;
-    }
-    __syncthreads();
-    // z += B y
-#pragma unroll 1
-    for (int r = lane; r < NPAD; r += 64) {
-      double s = 0.0;
-      static_for<0, M>([&](auto J) { s = fma(Bs[r * MS + J], sm.vec[1][J], s); });
-      sm.zs[r] += s;
-    }
-    __syncthreads();
+    double t = 0.0;
+    static_for<0, M>([&](auto J) { t = fma(-a[J], readlane_f64(rhs, J), t); });
+    const double dy = act ? t * sdiag : 0.0;
+    ysum += dy;
+    // z += B dy
+    static_for<0, NR>([&](auto R) {
+      const int r = lane + 64 * R;
+      if (r < NPAD) {
+        double s0 = 0.0, s1 = 0.0;
+        static_for<0, M>([&](auto J) {
+          if constexpr (J % 2 == 0) s0 = fma(Bs[r * MS + J], readlane_f64(dy, J), s0);
+          else s1 = fma(Bs[r * MS + J], readlane_f64(dy, J), s1);
+        });
+        zr[R] += s0 + s1;
+      }
+    });
     if (it == kRefine) break;
-    // residual of B^T z = F~, equilibrated; four accumulators break the latency chain
+    // residual of B^T z = F~, equilibrated; z goes through LDS, B^T is read by columns
+    static_for<0, NR>([&](auto R) {
+      const int r = lane + 64 * R;
+      if (r < NPAD) sm.zs[r] = zr[R];
+    });
+    __syncthreads();
     double res = 0.0;
     if (act) {
-      double r0 = sm.vec[0][lane], r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      double r0 = fv, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+#pragma unroll 4
       for (int r = 0; r < NPAD; r += 4) {
         r0 = fma(-Bs[(r + 0) * MS + lane], sm.zs[r + 0], r0);
         r1 = fma(-Bs[(r + 1) * MS + lane], sm.zs[r + 1], r1);
@@ -291,10 +293,15 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       }
       res = (r0 + r1) + (r2 + r3);
     }
-    __syncthreads();
-    if (act) sm.vec[1][lane] = res * sdiag;
+    rhs = res * sdiag;
     __syncthreads();
   }
+  static_for<0, NR>([&](auto R) {
+    const int r = lane + 64 * R;
+    if (r < NPAD) sm.zs[r] = zr[R];
+  });
+  if (act) sm.ys[lane] = ysum;
+  __syncthreads();
   return st;
 }
 
@@ -408,9 +415,10 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
     const double sb = (r < N) ? A.hscale * B.val_bar[fi.rp + r] : 0.0;
     zbar[r] = sm.wls[r] * sb;
   }
-  if (act) wv[lane] = 0.0;
   __syncthreads();
-  // w = G^-1 B^T zbar, refined:  w += G^-1 B^T (zbar - B w)
+  // w = G^-1 B^T zbar, refined:  w += G^-1 B^T (zbar - B w); lane p holds w_p
+  constexpr int NR = (NPAD + 63) / 64;
+  double wl = 0.0;
   for (int it = 0; it <= kRefine; ++it) {
     double res = 0.0;
     if (act) {
@@ -425,23 +433,26 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
       }
       res = (r0 + r1) + (r2 + r3);
     }
+    const double rhs = res * sdiag;
+    double t = 0.0;
+    static_for<0, M>([&](auto J) { t = fma(-a[J], readlane_f64(rhs, J), t); });
+    if (act) wl += t * sdiag;
     __syncthreads();
-    if (act) sm.vec[1][lane] = res * sdiag;
-    __syncthreads();
-    double dw = 0.0;
-    static_for<0, M>([&](auto J) { dw = fma(-a[J], sm.vec[1][J], dw); });
-    if (act) wv[lane] += dw * sdiag;
-    __syncthreads();
-    for (int r = lane; r < NPAD; r += 64) {
-      double s = 0.0;
-      static_for<0, M>([&](auto J) { s = fma(Bs[r * MS + J], wv[J], s); });
-      bw[r] = s;
-    }
+    static_for<0, NR>([&](auto R) {
+      const int r = lane + 64 * R;
+      if (r < NPAD) {
+        double s = 0.0;
+        static_for<0, M>([&](auto J) { s = fma(Bs[r * MS + J], readlane_f64(wl, J), s); });
+        bw[r] = s;
+      }
+    });
     __syncthreads();
   }
+  if (act) wv[lane] = wl;
+  __syncthreads();
   if (act) {
     yw[lane] = sm.ys[lane];
-    yw[M + lane] = wv[lane];
+    yw[M + lane] = wl;
   }
   // per row: r = zbar - B w;  Wbar;  (W r, W z) for the moment reduction;  EB x0 terms
   double gx[3] = {0, 0, 0};
