@@ -33,6 +33,31 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def qr_flops(N, M):
+    """Householder QR of an N x M matrix (LAPACK count)."""
+    return 2 * N * M * M - 2.0 / 3.0 * M**3
+
+
+def stream_copy_gbps(torch, dev, nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy bandwidth (read + write bytes / time), median of reps."""
+    import numpy as np
+
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del src, dst
+    return 2 * nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def householder_flops(N, M, T):
     """Per-face flop count of a backward-stable weighted least-squares stencil solve
     (LAPACK counts): Householder QR of the N x M weighted matrix, row assembly with T
@@ -47,10 +72,86 @@ def workload(name):
         return dict(shape=cg.ball_outside((0.5, 0.5, 0.5), 0.3), n=64, Q=4, R=3, seed=2,
                     desc="3D order 4: 64^3 unit cube minus sphere r=0.3 at (0.5,0.5,0.5), path radius 3, "
                          "35 monomials, Dirichlet, phi ~ N(0,1) seed 2")
+    if name == "c4":
+        return dict(n=48, Q=4, R=3, seed=3, n_geom=64,
+                    desc="3D order 4, batched: 64 unit cubes minus spheres, centres 0.5 + U(-0.05,0.05)^3, "
+                         "radii U(0.25,0.35) (default_rng(3): centres drawn first), 48^3 each, path radius 3, "
+                         "35 monomials")
     if name == "c1":
         return dict(shape=cg.ball_outside((0.5, 0.5), 0.25), n=32, Q=2, R=2, seed=2,
                     desc="2D order 2: 32^2 unit square minus disk r=0.25, path radius 2, 6 monomials")
     raise SystemExit(f"unknown workload {name}")
+
+
+def c4_shapes(w):
+    import numpy as np
+
+    import cutgeom as cg
+
+    rng = np.random.default_rng(w["seed"])
+    centres = 0.5 + rng.uniform(-0.05, 0.05, (w["n_geom"], 3))
+    radii = rng.uniform(0.25, 0.35, w["n_geom"])
+    return [cg.ball_outside(tuple(float(v) for v in c), float(r)) for c, r in zip(centres, radii)]
+
+
+def batched_comparison(steps):
+    """C4: all faces of 64 perturbed geometries in one build call (one launch per row-count
+    bin across every geometry, autotuned schedule) versus one build call per geometry.
+    Inputs are resident in HBM; each figure is the mean over `steps` builds."""
+    import numpy as np
+    import torch
+
+    import cutgeom as cg
+    import paper_1411_4283_amd as cc
+
+    w = workload("c4")
+    t0 = time.perf_counter()
+    hosts = [cg.make_geometry(s, w["n"], w["Q"]) for s in c4_shapes(w)]
+    log(f"c4: {len(hosts)} geometries in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    dgs = [cc.DeviceGeometry.from_host(h, dev) for h in hosts]
+    del hosts
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / n * 1e3
+
+    # one build call per geometry (each with its own launches, default schedule)
+    singles = [cc.Builder(dg, w["R"]) for dg in dgs]
+    outs = [b.allocate() for b in singles]
+    n_face = sum(b.sizes.n_face for b in singles)
+    nnz = sum(b.sizes.nnz for b in singles)
+    ms_single = timed(lambda: [b.build(out=o) for b, o in zip(singles, outs)], steps)
+    ref = [o.val[: o.sizes.nnz].clone() for o in outs[:2]]
+    del outs, singles
+    torch.cuda.empty_cache()
+    # the whole batch in one call: default schedule, then autotuned
+    bb = cc.Builder(dgs, w["R"])
+    st = bb.allocate()
+    assert st.sizes.n_face == n_face and st.sizes.nnz == nnz
+    ms_batch = timed(lambda: bb.build(out=st), steps)
+    tuning, best = bb.autotune(out=st)
+    ms_tuned = timed(lambda: bb.build(out=st), steps)
+    # the batch holds the same stencils as the separate builds (first two geometries)
+    off = 0
+    for r in ref:
+        assert torch.equal(st.val[off: off + r.numel()], r), "batched stencils differ from per-geometry ones"
+        off += r.numel()
+    sched = [(int(tuning.xcd_chunks[b]), int(tuning.blocks_per_xcd[b])) for b in range(8)]
+    out = {"workload": w["desc"], "n_geom": len(dgs), "n_face": int(n_face), "nnz": int(nnz),
+           "per_geometry_ms": ms_single, "batched_ms": ms_batch, "batched_autotuned_ms": ms_tuned,
+           "per_geometry_faces_per_s": n_face / (ms_single * 1e-3),
+           "batched_autotuned_faces_per_s": n_face / (ms_tuned * 1e-3),
+           "speedup_vs_per_geometry": ms_single / ms_tuned,
+           "schedule_per_bin": sched, "bin_best_ms": best}
+    del st, bb, dgs
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(g, R, sample, seed=7):
@@ -85,8 +186,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--cpu-sample", type=int, default=3000)
+    ap.add_argument("--cpu-sample", type=int, default=8000, help="faces of the oracle's timed sample (~10 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-geometry comparison")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design note, "
@@ -114,6 +217,11 @@ def main():
     lphi = torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=dev)
     flux = torch.empty(max(s.n_face, 1), dtype=torch.float64, device=dev)
     log(f"faces {s.n_face} nnz {s.nnz} phi {s.n_phi} max rows {s.max_rows}")
+    schedule = None
+    if not args.no_autotune:
+        tuning, best = b.autotune(out=st)
+        schedule = [(int(tuning.xcd_chunks[i]), int(tuning.blocks_per_xcd[i])) for i in range(8)]
+        log(f"autotuned schedule per bin (xcd chunks, blocks per xcd): {schedule}")
 
     for _ in range(args.warmup):
         b.build(out=st)
@@ -138,6 +246,16 @@ def main():
     t1 = time.perf_counter()
     _lib.set_profiling(False)
     apply_ms = [a.elapsed_time(z) for a, z in ev]
+    # the apply on its own: 3 warm-ups, median of 20 (HIP events on the launch stream)
+    for _ in range(3):
+        cc.apply(st, phi, lphi, flux)
+    ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for a, z in ev2:
+        a.record(stream)
+        cc.apply(st, phi, lphi, flux)
+        z.record(stream)
+    torch.cuda.synchronize()
+    apply_ms = [a.elapsed_time(z) for a, z in ev2]
     ms_per_step = (t1 - t0) / args.steps * 1e3
     log(f"ms/step {ms_per_step:.3f}  solve {np.mean(solve_ms):.3f} ms  apply {np.mean(apply_ms) * 1e3:.1f} us")
 
@@ -148,9 +266,11 @@ def main():
     status = st.status.cpu().numpy()[: s.n_face]
     ok = status == 0
     flops = float(np.sum(householder_flops(N[ok].astype(np.float64), M, T)))
+    flops_qr = float(np.sum(qr_flops(N[ok].astype(np.float64), M)))
     solve = float(np.mean(solve_ms))
     achieved_tf = flops / (solve * 1e-3) / 1e12
-    apply_mean = float(np.mean(apply_ms))
+    apply_mean = float(np.median(apply_ms))
+    copy_gbs = stream_copy_gbps(torch, dev)
     bytes_alg = 12 * s.nnz + 8 * (s.n_face + 1) + 8 * s.n_phi + 16 * s.n_vol
     apply_gbs = bytes_alg / (apply_mean * 1e-3) / 1e9
 
@@ -177,9 +297,18 @@ def main():
                            "frac": apply_gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "k_flux + k_divergence",
                            "kernel_ms": apply_mean, "bytes_per_launch": bytes_alg},
         "apply_gbps": apply_gbs,
+        "qr_only_tflops": flops_qr / (solve * 1e-3) / 1e12,
+        "stream_copy_gbps": copy_gbs,
+        "apply_frac_of_stream_copy": apply_gbs / copy_gbs,
         "build_faces_per_s": s.n_face / (float(np.mean([sum(v for v in p.values() if v > 0) for p in phases])) * 1e-3),
         "phases_ms": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
+        "schedule_per_bin": schedule,
     }
+    del st, b, dg
+    torch.cuda.empty_cache()
+    if not args.no_batched and args.workload == "c3":
+        log("batched comparison (64 geometries)")
+        out["batched"] = batched_comparison(max(1, min(args.steps, 3)))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, w["R"], args.cpu_sample)

@@ -76,7 +76,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 2
+#define CUTCELL_ABI_VERSION 3
 
 enum {
   CUTCELL_OK = 0,
@@ -101,12 +101,29 @@ enum {
 
 typedef void* cutcell_stream_t; /* hipStream_t */
 
+/* Launch schedule of the stencil solves, per row-count bin b (faces with
+ * 16 b < N <= 16 (b + 1) rows).  Results do not depend on it (every face is solved the
+ * same way); only the order in which workgroups take faces does.
+ *   xcd_chunks[b]     1: faces in bin order over the workgroups; 8: the bin is cut into
+ *                     8 contiguous chunks, one per XCD (MI355X deals workgroups to its 8
+ *                     XCDs in turn, each with its own L2), so faces that share rows share
+ *                     an L2.
+ *   blocks_per_xcd[b] 0: one workgroup per face; > 0: a persistent grid of
+ *                     xcd_chunks * blocks_per_xcd workgroups that walk their chunk.
+ * cutcell_autotune fills it by timing candidates on the caller's workload. */
+typedef struct {
+  int32_t xcd_chunks[8];
+  int32_t blocks_per_xcd[8];
+} cutcell_tuning;
+
 typedef struct {
   int32_t dim;          /* D: 2 or 3                                                   */
   int32_t n[3];         /* cells per direction (n[2] ignored when D = 2)               */
   double h;             /* grid spacing                                                */
   int32_t order;        /* Q: 2 or 4 (interpolant degree Q, P = Q + 1; Sec. 2.3)       */
   int32_t path_radius;  /* R_n, 1..4 (the paper uses 2 for Q = 2 and 3 for Q = 4)      */
+  const cutcell_tuning* tuning;  /* host pointer, or NULL for one workgroup per face in
+                                    bin order                                          */
 } cutcell_opts;
 
 /* One geometry: device arrays in the layouts above. */
@@ -158,6 +175,14 @@ int cutcell_query(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts*
 int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
                            const cutcell_sizes* sizes, cutcell_stencils* out,
                            void* workspace, size_t workspace_bytes, cutcell_stream_t stream);
+
+/* Builds the stencils like cutcell_build_stencils and, on the way, times every candidate
+ * schedule of each row-count bin (best of `reps` runs, HIP events on `stream`), writing the
+ * fastest to *tuning and each bin's best time in milliseconds to best_ms[8] (-1 for empty
+ * bins; may be NULL).  opts->tuning is ignored.  Synchronises `stream`. */
+int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                     const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
+                     int32_t reps, cutcell_tuning* tuning, double* best_ms, cutcell_stream_t stream);
 
 /* Applies the operator (Sec. 2.2, eq. 'laplacian over V'; Sec. 3.3):
  *   flux[f] = sum_j val[j] phi[col[j]]   (output, [n_face]; also the pass's scratch)

@@ -11,6 +11,13 @@ LIB_PATH = os.path.join(HERE, "libcutcell.so")
 P = ctypes.c_void_p
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("xcd_chunks", ctypes.c_int32 * 8),
+        ("blocks_per_xcd", ctypes.c_int32 * 8),
+    ]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32),
@@ -18,6 +25,7 @@ class Opts(ctypes.Structure):
         ("h", ctypes.c_double),
         ("order", ctypes.c_int32),
         ("path_radius", ctypes.c_int32),
+        ("tuning", ctypes.POINTER(Tuning)),
     ]
 
 
@@ -97,6 +105,9 @@ SIGNATURES = {
     "cutcell_build_stencils": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts),
                                               ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P,
                                               ctypes.c_size_t, P]),
+    "cutcell_autotune": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts),
+                                        ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P, ctypes.c_size_t,
+                                        ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double), P]),
     "cutcell_apply": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P, P, P, P]),
     "cutcell_transpose_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
     "cutcell_build_transpose": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays),

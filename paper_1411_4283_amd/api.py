@@ -13,7 +13,7 @@ from math import comb
 import torch
 
 from . import _lib
-from ._lib import Geom, GeomGrad, Opts, Sizes, StencilArrays, TransposeArrays, check, load
+from ._lib import Geom, GeomGrad, Opts, Sizes, StencilArrays, TransposeArrays, Tuning, check, load
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -196,6 +196,29 @@ class Builder:
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.device = device
         self.sizes = None
+        self.tuning = None
+
+    def set_tuning(self, tuning: "Tuning | None") -> None:
+        """Use a launch schedule (from autotune(), or None for the default)."""
+        self.tuning = tuning
+        self.opts.tuning = ctypes.pointer(tuning) if tuning is not None else None
+
+    def autotune(self, out: "Stencils | None" = None, reps: int = 2, stream=None):
+        """Time the candidate schedules of every row-count bin on these geometries, keep the
+        fastest (set_tuning) and return (tuning, best ms per bin).  `out` receives the
+        stencils, as from build()."""
+        if self.sizes is None:
+            self.query(stream)
+        out = self.allocate() if out is None else out
+        t = Tuning()
+        best = (ctypes.c_double * 8)()
+        arr = out.struct()
+        rc = load().cutcell_autotune(self.garr, len(self.geoms), ctypes.byref(self.opts), ctypes.byref(self.sizes),
+                                     ctypes.byref(arr), _ptr(self.workspace), self.workspace.numel(), int(reps),
+                                     ctypes.byref(t), best, _stream(stream))
+        out.code = check(rc, "cutcell_autotune")
+        self.set_tuning(t)
+        return t, [best[i] for i in range(8)]
 
     def query(self, stream=None) -> Sizes:
         sizes = Sizes()

@@ -100,6 +100,11 @@ static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
   if (o->order != 2 && o->order != 4) return fail(CUTCELL_E_UNSUPPORTED, "order must be 2 or 4");
   if (o->path_radius < 1 || o->path_radius > 4) return fail(CUTCELL_E_UNSUPPORTED, "path_radius must be in [1, 4]");
   if (!(o->h > 0)) return fail(CUTCELL_E_INVALID_ARG, "h must be positive");
+  if (o->tuning)
+    for (int b = 0; b < kMaxBins; ++b)
+      if (o->tuning->xcd_chunks[b] < 0 || o->tuning->xcd_chunks[b] > 64 || o->tuning->blocks_per_xcd[b] < 0 ||
+          o->tuning->blocks_per_xcd[b] > (1 << 24))
+        return fail(CUTCELL_E_INVALID_ARG, "tuning entries out of range");
   for (int d = 0; d < o->dim; ++d)
     if (o->n[d] < 1 || o->n[d] > (1 << 14)) return fail(CUTCELL_E_INVALID_ARG, "n[d] out of range");
   long long ncell = 1;
@@ -285,9 +290,9 @@ int cutcell_query(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts*
   return CUTCELL_OK;
 }
 
-int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
-                           const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
-                           cutcell_stream_t stream) {
+static int build_common(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                        const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
+                        cutcell_stream_t stream, cutcell_tuning* tune_out, int reps, double* best_ms) {
   if (!sizes || !out) return fail(CUTCELL_E_INVALID_ARG, "sizes/out is NULL");
   if (!out->row_ptr || !out->col || !out->val || !out->status || !out->vol_face || !out->vol_scale ||
       !out->phi_off || !out->vol_off || !out->face_off)
@@ -321,7 +326,14 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
   int32_t bc[kBinWords];
   CC_HIP(hipMemcpyAsync(bc, w.bins, sizeof(bc), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
-  rc = solve_stencils(w, *opts, bc, P.n_face, out->row_ptr, out->col, out->val, out->status, st);
+  if (tune_out) {
+    double bm[kMaxBins];
+    rc = tune_stencils(w, *opts, bc, out->row_ptr, out->col, out->val, out->status, st, tune_out, reps, bm);
+    if (best_ms)
+      for (int b = 0; b < kMaxBins; ++b) best_ms[b] = bm[b];
+  } else {
+    rc = solve_stencils(w, *opts, bc, P.n_face, out->row_ptr, out->col, out->val, out->status, st);
+  }
   if (rc) return rc;
   timer.mark();
   rc = volume_tables(w, *opts, P.n_vol, out->vol_face, out->vol_scale, st);
@@ -337,6 +349,23 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
   CC_HIP(hipGetLastError());
   timer.finish();
   return flagged ? CUTCELL_W_FLAGGED_FACES : CUTCELL_OK;
+}
+
+int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                           const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
+                           cutcell_stream_t stream) {
+  return build_common(geoms, n_geom, opts, sizes, out, workspace, workspace_bytes, stream, nullptr, 0, nullptr);
+}
+
+int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts, const cutcell_sizes* sizes,
+                     cutcell_stencils* out, void* workspace, size_t workspace_bytes, int32_t reps,
+                     cutcell_tuning* tuning, double* best_ms, cutcell_stream_t stream) {
+  if (!tuning) return fail(CUTCELL_E_INVALID_ARG, "tuning is NULL");
+  if (reps < 1 || reps > 100) return fail(CUTCELL_E_INVALID_ARG, "reps must be in [1, 100]");
+  if (!opts) return fail(CUTCELL_E_INVALID_ARG, "opts is NULL");
+  cutcell_opts o = *opts;
+  o.tuning = nullptr;
+  return build_common(geoms, n_geom, &o, sizes, out, workspace, workspace_bytes, stream, tuning, reps, best_ms);
 }
 
 void cutcell_set_profiling(int enable) { g_profiling = enable != 0; }

@@ -13,6 +13,7 @@ constexpr int kBinRows = 16;
 constexpr int kMaxRows = kMaxBins * kBinRows;
 constexpr int kNBuckets = kMaxBins + 1;   // the last bucket holds faces with N < M
 constexpr int kBinWords = 2 * kNBuckets + 1;  // counts, cursors, max rows
+constexpr int kXcds = 8;        // MI355X: workgroups are dealt to 8 XCDs (own L2 each) in turn
 
 // Per-batch workspace: pointers into the caller's buffer.
 struct Work {
@@ -109,6 +110,9 @@ struct ReduceArgs {
   const double* scale_bar;    // [n_vol] or null
 };
 
+int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
+                  const int32_t* col, double* val, int8_t* status, hipStream_t st, cutcell_tuning* out, int reps,
+                  double* best_ms);
 int backward_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
                       const int32_t* col, const BackwardArgs& bw, hipStream_t st);
 int rows_per_face(const Work& w, long long n_face, const int64_t* row_ptr, hipStream_t st);

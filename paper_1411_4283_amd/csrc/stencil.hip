@@ -17,6 +17,8 @@
 //   5. val = h^(D-2) W z.
 // Status: fewer rows than monomials, a pivot square root below 1e-7 times the largest after
 // equilibration (numerically rank deficient), or a non-finite entry flag the face.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "rows.hpp"
 
@@ -27,19 +29,16 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr double kRankTol = 1e-7;
 constexpr int kRefine = 2;
 
-// One row of B = W A~ about x0 (in units of h: x0h = x0 / h), with its weight.
-// Returns false if the row holds a non-finite value.
+// One row of B = W A~ about x0 (in units of h: x0h = x0 / h) from the row's stored
+// moments m (overwritten) and centre; returns its weight in w, and false if the row
+// holds a non-finite value.
 template <int D, int Q>
-__device__ __forceinline__ bool build_row(const GridDims& g, const GeomPtrs& gp, int64_t phi_local, int64_t n_vol,
-                                          int64_t n_eb, const int32_t* vol_cell, const int32_t* box_lf,
-                                          const double* x0h, double* m, double& w) {
+__device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h, double* m, double& w) {
   constexpr int M = Dims<D, Q>::M;
-  const RowSource rs = row_source<D, Q>(g, gp, phi_local, n_vol, n_eb, vol_cell, box_lf);
-  load_row_moments<D, Q>(rs, m);
   double delta[3] = {0, 0, 0};
   double d2 = 0;
   for (int ax = 0; ax < D; ++ax) {
-    delta[ax] = rs.ctr[ax] - x0h[ax];
+    delta[ax] = ctr[ax] - x0h[ax];
     d2 += delta[ax] * delta[ax];
   }
   w = row_weight(d2);
@@ -79,11 +78,11 @@ struct FaceInfo {
   int32_t owner_cell;        // EB faces: the cut cell
 };
 
-// x0, the flux vector F~ (in sm.vec[0]) and, for EB faces, the re-centred normal moments
-template <int D, int Q, int NPAD>
-__device__ __forceinline__ void face_setup(const GridDims& g, const GeomPtrs& gp, FaceInfo& fi,
-                                           FaceSmem<D, Q, NPAD>& sm, int lane) {
-  constexpr int M = Dims<D, Q>::M, Mf = Dims<D, Q>::Mf, M1 = Dims<D, Q>::M1;
+// x0 of the face (in units of h): the face centre, or for an EB face the centroid of its
+// cut volume (whose offset from the cell centre is kept in fi.off).  Loads only.
+template <int D, int Q>
+__device__ __forceinline__ void face_x0(const GridDims& g, const GeomPtrs& gp, FaceInfo& fi) {
+  constexpr int M = Dims<D, Q>::M;
   const int dn = fi.dn;
   for (int ax = 0; ax < 3; ++ax) { fi.x0h[ax] = 0.0; fi.off[ax] = 0.0; }
   fi.owner_cell = -1;
@@ -92,8 +91,29 @@ __device__ __forceinline__ void face_setup(const GridDims& g, const GeomPtrs& gp
     const int m0 = g.n[0] + (dn == 0), m1 = g.n[1] + (dn == 1);
     const int j[3] = {(int)(loc % m0), (int)((loc / m0) % m1), (int)(loc / ((long long)m0 * m1))};
     for (int ax = 0; ax < D; ++ax) fi.x0h[ax] = (ax == dn) ? (double)j[ax] : j[ax] + 0.5;
+    return;
+  }
+  const int32_t c = gp.eb_cell[fi.ref];
+  fi.owner_cell = c;
+  const int cown[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+  const double* vm = gp.vol_mom + (long long)c * M;
+  const double k0 = vm[0];
+  for (int ax = 0; ax < D; ++ax) {
+    fi.off[ax] = vm[1 + ax] / k0;          // first moments: degree-1 monomials e_1..e_D
+    fi.x0h[ax] = cown[ax] + 0.5 + fi.off[ax];
+  }
+}
+
+// The flux vector F~ (in sm.vec[0]) and, for EB faces, the normal moments re-centred to x0
+// (sm.nus, lanes 0..D-1 one component each).
+template <int D, int Q, int NPAD>
+__device__ __forceinline__ void face_flux(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
+                                          FaceSmem<D, Q, NPAD>& sm, int lane) {
+  constexpr int M = Dims<D, Q>::M, Mf = Dims<D, Q>::Mf, M1 = Dims<D, Q>::M1;
+  const int dn = fi.dn;
+  if (fi.kind == 0) {
     // F~_p = face moment of p - e_d when p_d = 1 (reference normal +e_d)
-    const double* fm = gp.face_mom[dn] + loc * Mf;
+    const double* fm = gp.face_mom[dn] + (fi.ref - g.foff[dn]) * Mf;
     if (lane < M) {
       double fv = 0.0;
       constexpr auto& T = kMono<D, Q>;
@@ -111,17 +131,6 @@ __device__ __forceinline__ void face_setup(const GridDims& g, const GeomPtrs& gp
     }
     __syncthreads();
     return;
-  }
-  // EB face: x0 = centroid of the cut volume; the normal moments (about the cell centre)
-  // are re-centred to x0 by lanes 0..D-1, one component each
-  const int32_t c = gp.eb_cell[fi.ref];
-  fi.owner_cell = c;
-  const int cown[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
-  const double* vm = gp.vol_mom + (long long)c * M;
-  const double k0 = vm[0];
-  for (int ax = 0; ax < D; ++ax) {
-    fi.off[ax] = vm[1 + ax] / k0;          // first moments: degree-1 monomials e_1..e_D
-    fi.x0h[ax] = cown[ax] + 0.5 + fi.off[ax];
   }
   if (lane < D) {
     double nu[M1];
@@ -163,51 +172,68 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   const int N = fi.N;
 
   // ---- rows of B ----------------------------------------------------------------------
+  // Lane r builds rows r, r + 64, ...: every row's index chain (col -> cell -> moments) is
+  // issued before the first row is finished, so the dependent loads of all rows overlap.
+  constexpr int NR = (NPAD + 63) / 64;
   bool finite = true;
-#pragma unroll 1
-  for (int r = lane; r < NPAD; r += 64) {
-    double m[M];
-    double wr = 0.0;
-    if (r < N) {
-      const int64_t loc = (int64_t)col[fi.rp + r] - fi.phi0;
-      finite = build_row<D, Q>(g, gp, loc, fi.n_vol, fi.n_eb, vol_cell, box_lf, fi.x0h, m, wr) && finite;
-    } else {
-      static_for<0, M>([&](auto I) { m[I] = 0.0; });
+  RowSource rsrc[NR];
+  static_for<0, NR>([&](auto R) {
+    const int r = lane + 64 * R;
+    if (r < N) rsrc[R] = row_source<D, Q>(g, gp, (int64_t)col[fi.rp + r] - fi.phi0, fi.n_vol, fi.n_eb, vol_cell,
+                                          box_lf);
+  });
+  static_for<0, NR>([&](auto R) {
+    const int r = lane + 64 * R;
+    if (r < NPAD) {
+      double m[M];
+      double wr = 0.0;
+      if (r < N) {
+        load_row_moments<D, Q>(rsrc[R], m);
+        finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr) && finite;
+      } else {
+        static_for<0, M>([&](auto I) { m[I] = 0.0; });
+      }
+      static_for<0, M>([&](auto I) { Bs[r * MS + I] = m[I]; });
+      sm.wls[r] = wr;
+      sm.zs[r] = 0.0;
     }
-    static_for<0, M>([&](auto I) { Bs[r * MS + I] = m[I]; });
-    sm.wls[r] = wr;
-    sm.zs[r] = 0.0;
-  }
-  __syncthreads();
+  });
+  face_flux<D, Q, NPAD>(g, gp, fi, sm, lane);
   const bool allfinite = __all(finite) && __all(lane >= M || isfinite(sm.vec[0][lane < M ? lane : 0]));
 
-  // ---- G = B^T B on the matrix cores ----------------------------------------------------
-  dbl4 acc[MT][MT];
+  // ---- G = B^T B: full 16-column tiles on the matrix cores --------------------------------
+  // (v_mfma_f64_16x16x4f64, upper triangle of tiles, rows of B as the contraction index).
+  // A narrow trailing block (at most 4 columns, e.g. 3 of M = 35) is done on the vector
+  // ALUs instead: as a 16-wide tile it would be mostly padding, and FP64 MFMA has no more
+  // throughput than FP64 FMA on this chip.
+  constexpr int MTF = (MT > 1 && M - 16 * (MT - 1) <= 4) ? MT - 1 : MT;
+  constexpr int MV = M - 16 * MTF;
+  dbl4 acc[MTF][MTF];
 #pragma unroll
-  for (int i = 0; i < MT; ++i)
+  for (int i = 0; i < MTF; ++i)
 #pragma unroll
-    for (int j = 0; j < MT; ++j) acc[i][j] = dbl4{0, 0, 0, 0};
+    for (int j = 0; j < MTF; ++j) acc[i][j] = dbl4{0, 0, 0, 0};
   const int lr = lane >> 4, lc = lane & 15;
 #pragma unroll
   for (int k0 = 0; k0 < NPAD; k0 += 4) {
-    double x[MT];
+    double x[MTF];
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
+    for (int i = 0; i < MTF; ++i) {
       const int cidx = 16 * i + lc;
       x[i] = (cidx < M) ? Bs[(k0 + lr) * MS + cidx] : 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < MT; ++i)
+    for (int i = 0; i < MTF; ++i)
 #pragma unroll
-      for (int j = i; j < MT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], x[j], acc[i][j], 0, 0, 0);
+      for (int j = i; j < MTF; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], x[j], acc[i][j], 0, 0, 0);
   }
   // tile (i, j), register q holds G[16i + lane/16 + 4q][16j + lane%16] (the output layout
   // of v_mfma_f64_16x16x4f64); each entry of the symmetric matrix is written once
   // (r <= c) together with its mirror
 #pragma unroll
-  for (int i = 0; i < MT; ++i)
+  for (int i = 0; i < MTF; ++i)
 #pragma unroll
-    for (int j = i; j < MT; ++j)
+    for (int j = i; j < MTF; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = 16 * i + lr + 4 * q, c = 16 * j + lc;
@@ -216,6 +242,25 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
           Ls[c * MS + r] = acc[i][j][q];
         }
       }
+  if constexpr (MV > 0) {
+    // lane l: G[l][16 MTF + c] for the trailing columns c (and the mirrored entries)
+    if (lane < M) {
+      double g0[MV], g1[MV];
+      static_for<0, MV>([&](auto C) { g0[C] = 0.0; g1[C] = 0.0; });
+      for (int k = 0; k < NPAD; k += 2) {
+        const double b0 = Bs[k * MS + lane], b1 = Bs[(k + 1) * MS + lane];
+        static_for<0, MV>([&](auto C) {
+          g0[C] = fma(b0, Bs[k * MS + 16 * MTF + C], g0[C]);
+          g1[C] = fma(b1, Bs[(k + 1) * MS + 16 * MTF + C], g1[C]);
+        });
+      }
+      static_for<0, MV>([&](auto C) {
+        const double v = g0[C] + g1[C];
+        Ls[lane * MS + 16 * MTF + C] = v;
+        Ls[(16 * MTF + C) * MS + lane] = v;
+      });
+    }
+  }
   __syncthreads();
 
   // ---- equilibrate to unit diagonal and invert: lane i holds row i ----------------------------
@@ -228,6 +273,9 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   sdiag = act ? 1.0 / sqrt(Ls[li * MS + li]) : 1.0;
   static_for<0, M>([&](auto J) { a[J] = act ? Ls[li * MS + J] * sdiag * readlane_f64(sdiag, J) : 0.0; });
   double pmax = 0.0, pmin = 1e300;
+  // Step k:  a_ij -= (a_ik / d) a_kj  (i, j != k);  a_ik /= d;  a_kj /= d;  a_kk = -1/d.
+  // Each lane scales its multiplier once (u = a_ik / d; on lane k, 1 - 1/d turns the
+  // pivot row into a_kj / d), so every entry is one FMA fed straight by v_readlane.
   static_for<0, M>([&](auto K) {
     constexpr int k = K;
     const double d = readlane_f64(a[k], k);
@@ -235,13 +283,12 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     pmax = fmax(pmax, sq);
     pmin = fmin(pmin, sq);
     const double rd = 1.0 / d;
-    const double u = (lane == k) ? d - 1.0 : a[k];      // a_ik (before this step)
+    const double u = (lane == k) ? 1.0 - rd : a[k] * rd;
     static_for<0, M>([&](auto J) {
       constexpr int j = J;
-      const double wj = (j == k) ? 1.0 - rd : readlane_f64(a[j], k) * rd;
-      a[j] = fma(-u, wj, a[j]);
+      if constexpr (j != k) a[j] = fma(-u, readlane_f64(a[j], k), a[j]);
     });
-    if (lane == k) a[k] = -rd;
+    a[k] = (lane == k) ? -rd : u;
   });
   const bool rankok = (pmin > kRankTol * pmax) && (pmax > 0.0);
   int st = CUTCELL_STATUS_OK;
@@ -251,27 +298,24 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   // ---- semi-normal solve with refinement ----------------------------------------------------
   // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs).  Lane p holds
   // component p of F~, rhs and y; lane r holds z of its rows r, r + 64.
-  constexpr int NR = (NPAD + 63) / 64;
   const double fv = act ? sm.vec[0][lane] : 0.0;
   double rhs = fv * sdiag;
   double ysum = 0.0;
   double zr[NR];
   static_for<0, NR>([&](auto R) { zr[R] = 0.0; });
   for (int it = 0; it <= kRefine; ++it) {
-    double t = 0.0;
-    static_for<0, M>([&](auto J) { t = fma(-a[J], readlane_f64(rhs, J), t); });
+    double tq[4] = {0.0, 0.0, 0.0, 0.0};
+    static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], readlane_f64(rhs, J), tq[J % 4]); });
+    const double t = (tq[0] + tq[1]) + (tq[2] + tq[3]);
     const double dy = act ? t * sdiag : 0.0;
     ysum += dy;
     // z += B dy
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
       if (r < NPAD) {
-        double s0 = 0.0, s1 = 0.0;
-        static_for<0, M>([&](auto J) {
-          if constexpr (J % 2 == 0) s0 = fma(Bs[r * MS + J], readlane_f64(dy, J), s0);
-          else s1 = fma(Bs[r * MS + J], readlane_f64(dy, J), s1);
-        });
-        zr[R] += s0 + s1;
+        double sq4[4] = {0.0, 0.0, 0.0, 0.0};
+        static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], readlane_f64(dy, J), sq4[J % 4]); });
+        zr[R] += (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
       }
     });
     if (it == kRefine) break;
@@ -320,6 +364,30 @@ struct StencilArgs {
   const int32_t* box_lf_ws;
   const int64_t* row_ptr;
   const int32_t* col;
+  // schedule: workgroup b runs on XCD b % xcd (the dispatcher deals workgroups out to the
+  // XCDs in turn) and walks that XCD's contiguous chunk of the bin with stride per_xcd
+  int xcd;
+  int per_xcd;
+};
+
+// Faces of a bin taken by workgroup blockIdx.x in turn (-1 when done).  With xcd = 1 and a
+// grid of nbin workgroups this is one face per workgroup in bin order.
+struct FaceWalk {
+  long long chunk, k, base;
+  int step;
+  __device__ FaceWalk(const StencilArgs& A) {
+    const int b = blockIdx.x;
+    chunk = (A.nbin + A.xcd - 1) / A.xcd;
+    base = (long long)(b % A.xcd) * chunk;
+    k = b / A.xcd;
+    step = A.per_xcd;
+  }
+  __device__ long long next() {
+    if (k >= chunk) return -1;
+    const long long t = base + k;
+    k += step;
+    return t;
+  }
 };
 
 __device__ __forceinline__ FaceInfo face_info(const StencilArgs& A, long long t) {
@@ -338,17 +406,16 @@ __device__ __forceinline__ FaceInfo face_info(const StencilArgs& A, long long t)
   return fi;
 }
 
+// One face per workgroup (WALK = false: face t of the bin, t from the XCD mapping), or a
+// persistent workgroup that walks its chunk (WALK = true).  Two instances because the
+// loop costs the single-face kernel registers.
 template <int D, int Q, int NPAD>
-__global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restrict__ val, int8_t* __restrict__ status,
-                                               int32_t* flagged) {
+__device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, FaceSmem<D, Q, NPAD>& sm, int lane,
+                                             double* __restrict__ val, int8_t* __restrict__ status, int32_t* flagged) {
   constexpr int M = Dims<D, Q>::M;
-  __shared__ FaceSmem<D, Q, NPAD> sm;
-  const long long t = blockIdx.x;
-  if (t >= A.nbin) return;
-  const int lane = threadIdx.x;
   FaceInfo fi = face_info(A, t);
   const GeomPtrs gp = A.geoms[fi.gi];
-  face_setup<D, Q, NPAD>(A.g, gp, fi, sm, lane);
+  face_x0<D, Q>(A.g, gp, fi);
   double a[M];
   double sdiag;
   const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
@@ -358,6 +425,23 @@ __global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restric
   if (lane == 0) {
     status[fi.F] = (int8_t)st;
     if (st != CUTCELL_STATUS_OK) atomicAdd(flagged, 1);
+  }
+}
+
+template <int D, int Q, int NPAD, bool WALK>
+__global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restrict__ val, int8_t* __restrict__ status,
+                                               int32_t* flagged) {
+  __shared__ FaceSmem<D, Q, NPAD> sm;
+  const int lane = threadIdx.x;
+  FaceWalk walk(A);
+  if constexpr (!WALK) {
+    const long long t = walk.next();
+    if (t >= 0 && t < A.nbin) stencil_face<D, Q, NPAD>(A, t, sm, lane, val, status, flagged);
+  } else {
+    for (long long t = walk.next(); t >= 0 && t < A.nbin; t = walk.next()) {
+      stencil_face<D, Q, NPAD>(A, t, sm, lane, val, status, flagged);
+      __syncthreads();   // the next face reuses the shared memory
+    }
   }
 }
 
@@ -388,7 +472,7 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
   const int lane = threadIdx.x;
   FaceInfo fi = face_info(A, t);
   const GeomPtrs gp = A.geoms[fi.gi];
-  face_setup<D, Q, NPAD>(A.g, gp, fi, sm, lane);
+  face_x0<D, Q>(A.g, gp, fi);
   double a[M];
   double sdiag;
   const int32_t* vol_cell = A.vol_cell_ws + (long long)fi.gi * A.g.ncell;
@@ -434,9 +518,9 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
       res = (r0 + r1) + (r2 + r3);
     }
     const double rhs = res * sdiag;
-    double t = 0.0;
-    static_for<0, M>([&](auto J) { t = fma(-a[J], readlane_f64(rhs, J), t); });
-    if (act) wl += t * sdiag;
+    double tq[4] = {0.0, 0.0, 0.0, 0.0};
+    static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], readlane_f64(rhs, J), tq[J % 4]); });
+    if (act) wl += ((tq[0] + tq[1]) + (tq[2] + tq[3])) * sdiag;
     __syncthreads();
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
@@ -580,6 +664,8 @@ __global__ void k_insufficient(const int32_t* __restrict__ perm, long long n, co
 static StencilArgs stencil_args(const Work& w, double hscale, const int32_t* perm, long long nbin,
                                 const int64_t* row_ptr, const int32_t* col) {
   StencilArgs A;
+  A.xcd = 1;
+  A.per_xcd = 1;
   A.g = w.dims;
   A.G = w.G;
   A.hscale = hscale;
@@ -615,41 +701,61 @@ __global__ void k_insufficient_backward(const int32_t* __restrict__ perm, long l
   }
 }
 
+// Launch shape of one bin: xcd = 1 or the number of XCDs whose chunks the bin is split
+// into; per_xcd = 0 for one workgroup per face, else the persistent workgroups per chunk.
+struct BinSchedule {
+  int xcd = 1;
+  int per_xcd = 0;
+};
+
 template <int D, int Q, int NPAD>
 static void launch_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, const int64_t* row_ptr,
-                       const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw) {
+                       const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
+                       BinSchedule sc) {
   if (nbin <= 0) return;
-  const StencilArgs A = stencil_args(w, hscale, perm, nbin, row_ptr, col);
-  if (bw)
+  StencilArgs A = stencil_args(w, hscale, perm, nbin, row_ptr, col);
+  if (bw) {
     hipLaunchKernelGGL((k_stencil_backward<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, A, *bw);
+    return;
+  }
+  const int X = sc.xcd > 1 ? sc.xcd : 1;
+  const long long chunk = (nbin + X - 1) / X;
+  const long long per = sc.per_xcd > 0 ? std::min<long long>(sc.per_xcd, chunk) : chunk;
+  A.xcd = X;
+  A.per_xcd = (int)per;
+  if (per < chunk)
+    hipLaunchKernelGGL((k_stencil<D, Q, NPAD, true>), dim3((unsigned)(X * per)), dim3(64), 0, st, A, val, status,
+                       w.flagged);
   else
-    hipLaunchKernelGGL((k_stencil<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, A, val, status, w.flagged);
+    hipLaunchKernelGGL((k_stencil<D, Q, NPAD, false>), dim3((unsigned)(X * per)), dim3(64), 0, st, A, val, status,
+                       w.flagged);
 }
 
 template <int D, int Q>
 static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count, const int64_t* row_ptr,
-                         const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw) {
+                         const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
+                         const BinSchedule* sched, int only_bin) {
   constexpr int M = binom(Q + D, D);
   long long start = 0;
   for (int b = 0; b < kMaxBins; ++b) {
     const long long nb = bin_count[b];
     const int32_t* p = w.perm + start;
     start += nb;
-    if (nb == 0) continue;
+    if (nb == 0 || (only_bin >= 0 && b != only_bin)) continue;
     const int npad = kBinRows * (b + 1);
     if (npad < M) return fail(CUTCELL_E_INVALID_ARG, "internal: face with N >= M in a bin narrower than M");
     switch (npad) {
-      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
-      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw); break;
+      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
     }
   }
-  const long long ninsuf = bin_count[kMaxBins];
+  const long long ninsuf = (only_bin < 0) ? bin_count[kMaxBins] : 0;
   if (ninsuf > 0 && bw)
     hipLaunchKernelGGL(k_insufficient_backward, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st,
                        w.perm + start, ninsuf, row_ptr, (int)M, *bw);
@@ -661,25 +767,94 @@ static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count,
 }
 
 static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
-                    const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw) {
+                    const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
+                    const BinSchedule* sched, int only_bin = -1) {
   double hscale = 1.0;
   for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
-  if (o.dim == 2 && o.order == 2) return dispatch_bins<2, 2>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
-  if (o.dim == 2 && o.order == 4) return dispatch_bins<2, 4>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
-  if (o.dim == 3 && o.order == 2) return dispatch_bins<3, 2>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
-  if (o.dim == 3 && o.order == 4) return dispatch_bins<3, 4>(w, hscale, bin_count, row_ptr, col, val, status, st, bw);
+#define CC_RB(DD, QQ) \
+  if (o.dim == DD && o.order == QQ) \
+    return dispatch_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin);
+  CC_RB(2, 2) CC_RB(2, 4) CC_RB(3, 2) CC_RB(3, 4)
+#undef CC_RB
   return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");
+}
+
+static void schedules_from(const cutcell_tuning* t, BinSchedule* sc) {
+  for (int b = 0; b < kMaxBins; ++b) {
+    sc[b] = BinSchedule{};
+    if (t) {
+      sc[b].xcd = t->xcd_chunks[b] > 1 ? t->xcd_chunks[b] : 1;
+      sc[b].per_xcd = t->blocks_per_xcd[b] > 0 ? t->blocks_per_xcd[b] : 0;
+    }
+  }
 }
 
 int solve_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, long long n_face,
                    const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st) {
   (void)n_face;
-  return run_bins(w, o, bin_count, row_ptr, col, val, status, st, nullptr);
+  BinSchedule sc[kMaxBins];
+  schedules_from(o.tuning, sc);
+  return run_bins(w, o, bin_count, row_ptr, col, val, status, st, nullptr, sc);
 }
 
 int backward_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
                       const int32_t* col, const BackwardArgs& bw, hipStream_t st) {
-  return run_bins(w, o, bin_count, row_ptr, col, nullptr, nullptr, st, &bw);
+  BinSchedule sc[kMaxBins];
+  schedules_from(nullptr, sc);
+  return run_bins(w, o, bin_count, row_ptr, col, nullptr, nullptr, st, &bw, sc);
+}
+
+// Times every candidate schedule of every non-empty bin on these faces (HIP events, best
+// of `reps`) and keeps the fastest; then solves all bins with the chosen schedules, so
+// val/status hold the same stencils as an untuned build.
+int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
+                  const int32_t* col, double* val, int8_t* status, hipStream_t st, cutcell_tuning* out, int reps,
+                  double* best_ms) {
+  int dev = 0, cus = 256;
+  CC_HIP(hipGetDevice(&dev));
+  CC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int X = kXcds;
+  const int resident = std::max(1, cus / X) * 4;   // workgroups per XCD at one wave per SIMD
+  const BinSchedule cand[] = {{1, 0}, {X, 0}, {X, resident}, {X, 2 * resident}, {1, X * resident}};
+  const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+  hipEvent_t e0, e1;
+  CC_HIP(hipEventCreate(&e0));
+  CC_HIP(hipEventCreate(&e1));
+  BinSchedule sc[kMaxBins];
+  schedules_from(nullptr, sc);
+  for (int b = 0; b < kMaxBins; ++b) {
+    best_ms[b] = -1.0;
+    if (bin_count[b] == 0) continue;
+    double best = 1e300;
+    for (int c = 0; c < ncand; ++c) {
+      BinSchedule trial[kMaxBins];
+      for (int i = 0; i < kMaxBins; ++i) trial[i] = cand[c];
+      double tmin = 1e300;
+      for (int r = 0; r < reps; ++r) {
+        CC_HIP(hipEventRecord(e0, st));
+        int rc = run_bins(w, o, bin_count, row_ptr, col, val, status, st, nullptr, trial, b);
+        if (rc) return rc;
+        CC_HIP(hipEventRecord(e1, st));
+        CC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        tmin = std::min(tmin, (double)ms);
+      }
+      if (tmin < best) {
+        best = tmin;
+        sc[b] = cand[c];
+      }
+    }
+    best_ms[b] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int b = 0; b < kMaxBins; ++b) {
+    out->xcd_chunks[b] = sc[b].xcd;
+    out->blocks_per_xcd[b] = sc[b].per_xcd;
+  }
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.flagged, 1LL, 0);
+  return run_bins(w, o, bin_count, row_ptr, col, val, status, st, nullptr, sc);
 }
 
 }  // namespace cutcell

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 2
+    assert lib.cutcell_abi_version() == 3
 
 
 def _opts(**kw):

@@ -256,3 +256,30 @@ def test_bad_eb_cells_rejected():
     with pytest.raises(cc.CutcellError) as e:
         cc.Builder(dg, 2).query()
     assert e.value.code == -1
+
+
+def test_every_schedule_gives_identical_stencils():
+    """The launch schedule (faces in bin order or in per-XCD chunks, one workgroup per
+    face or a persistent grid) changes only which workgroup takes a face: val and status
+    must be bit-identical to the default build, and the autotuned build as well."""
+    from paper_1411_4283_amd._lib import Tuning
+
+    g = cg.make_geometry(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 24, 4)
+    dg, b, st0 = _gpu_build(g, 3)
+    val0, status0 = st0.val.clone(), st0.status.clone()
+    for xcd, per in [(8, 0), (8, 16), (8, 100), (1, 64), (3, 5)]:
+        t = Tuning()
+        for i in range(8):
+            t.xcd_chunks[i], t.blocks_per_xcd[i] = xcd, per
+        b.set_tuning(t)
+        _say(f"schedule xcd={xcd} per={per}")
+        st = b.build()
+        torch.cuda.synchronize()
+        assert torch.equal(st.val, val0) and torch.equal(st.status, status0), (xcd, per)
+    b.set_tuning(None)
+    tuning, best = b.autotune()
+    st = b.build()
+    torch.cuda.synchronize()
+    _say(f"autotuned {[(tuning.xcd_chunks[i], tuning.blocks_per_xcd[i]) for i in range(8)]} best {best}")
+    assert torch.equal(st.val, val0) and torch.equal(st.status, status0)
+    assert any(x > 0 for x in best)
