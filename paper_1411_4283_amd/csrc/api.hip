@@ -78,6 +78,8 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   t.box_lf = (int32_t*)take(sizeof(int32_t) * G * std::max<long long>(g.nboxslot, 1));
   t.vol_cell = (int32_t*)take(sizeof(int32_t) * G * g.ncell);
   t.cellinfo = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
+  t.ballreg = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
+  t.ballreg_tmp = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
   t.counts = (int64_t*)take(sizeof(int64_t) * 4 * G);
   t.offs = (int64_t*)take(sizeof(int64_t) * 3 * (G + 1));
   t.fcode = (int32_t*)take(sizeof(int32_t) * totface);

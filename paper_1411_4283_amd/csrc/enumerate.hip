@@ -31,12 +31,13 @@ __device__ __forceinline__ int lattice_dir(const GridDims& g, long long lf) {
   return (lf >= g.foff[1]) + (lf >= g.foff[2]);
 }
 
+// (32-bit arithmetic: a geometry's lattice has fewer than 2^31 faces, checked on entry)
 __device__ __forceinline__ void lattice_coords(const GridDims& g, int d, long long lf, int* j) {
-  long long loc = lf - g.foff[d];
-  int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
-  j[0] = (int)(loc % m0);
-  j[1] = (int)((loc / m0) % m1);
-  j[2] = (int)(loc / ((long long)m0 * m1));
+  const int loc = (int)(lf - g.foff[d]);
+  const int m0 = g.n[0] + (d == 0), m1 = g.n[1] + (d == 1);
+  j[0] = loc % m0;
+  j[1] = (loc / m0) % m1;
+  j[2] = loc / (m0 * m1);
 }
 
 __device__ __forceinline__ long long lattice_index(const GridDims& g, int d, const int* j) {
@@ -178,6 +179,36 @@ __global__ void k_cellinfo(GridDims g, const int32_t* __restrict__ vol_id, const
   info[o] = (uint8_t)v;
 }
 
+// Regular cells for the neighbour fast path: reg0 = a volume without an EB face whose 2D
+// faces are all flux faces and which does not touch the box boundary; then R erosions,
+// reg_{k+1}(c) = reg_k(c) and reg_k of its 2D neighbours, so reg_R(c) = 1 iff every cell
+// within L1 distance R of c is regular.  For such cells the path-distance ball of radius
+// R is the L1 ball and touches no EB or box face.
+__global__ void k_regular0(GridDims g, const uint8_t* __restrict__ info, uint8_t* __restrict__ reg) {
+  const int gi = blockIdx.y;
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long long o = (long long)gi * g.ncell + c;
+  const unsigned full = (1u << (1 + 2 * g.D)) - 1u;   // volume bit and all open-face bits
+  bool r = info[o] == full;
+  const int x[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+  for (int d = 0; d < g.D; ++d) r = r && x[d] >= 1 && x[d] <= g.n[d] - 2;
+  reg[o] = r ? 1 : 0;
+}
+
+__global__ void k_erode(GridDims g, const uint8_t* __restrict__ in, uint8_t* __restrict__ out) {
+  const int gi = blockIdx.y;
+  long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long long o = (long long)gi * g.ncell + c;
+  bool r = in[o] != 0;   // a regular cell is interior, so its neighbours exist
+  if (r) {
+    const long long st[3] = {1, g.n[0], (long long)g.n[0] * g.n[1]};
+    for (int d = 0; d < g.D; ++d) r = r && in[o - st[d]] && in[o + st[d]];
+  }
+  out[o] = r ? 1 : 0;
+}
+
 int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st) {
   const GridDims& g = w.dims;
   const int D = o.dim, Q = o.order;
@@ -198,6 +229,14 @@ int enumerate_batch(const Work& w, const cutcell_opts& o, hipStream_t st) {
                      w.eb_id, w.fcode, w.fref);
   hipLaunchKernelGGL(k_cellinfo, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, w.vol_id, w.eb_id, w.face_id,
                      w.cellinfo);
+  // the result must end in w.ballreg: start in the buffer that R erosions leave it in
+  uint8_t* bufs[2] = {w.ballreg, w.ballreg_tmp};
+  int cur = (o.path_radius % 2 == 0) ? 0 : 1;
+  hipLaunchKernelGGL(k_regular0, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, w.cellinfo, bufs[cur]);
+  for (int r = 0; r < o.path_radius; ++r) {
+    hipLaunchKernelGGL(k_erode, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, bufs[cur], bufs[1 - cur]);
+    cur = 1 - cur;
+  }
   CC_HIP(hipGetLastError());
   return CUTCELL_OK;
 }
@@ -213,6 +252,42 @@ struct Win {
   static constexpr int K = (NW + 63) / 64;                   // window cells per lane
 };
 
+// Rows of a face between two ball-regular cells a (low) and a + e_d: the union of the L1
+// balls of radius R around them, as offsets from a in ascending cell-index order (z, y, x).
+template <int D, int R>
+struct RegularRows {
+  static constexpr int kMax = 2 * (2 * R + 2) * (2 * R + 1) * (D == 3 ? 2 * R + 1 : 1);
+  int n = 0;
+  int8_t off[3][kMax][3] = {};
+  constexpr RegularRows() {
+    for (int dn = 0; dn < D; ++dn) {
+      int cnt = 0;
+      const int zlo = (D == 3) ? -R : 0, zhi = (D == 3) ? R + (dn == 2) : 0;
+      for (int z = zlo; z <= zhi; ++z)
+        for (int y = -R; y <= R + (dn == 1); ++y)
+          for (int x = -R; x <= R + (dn == 0); ++x) {
+            const int o[3] = {x, y, z};
+            int l0 = 0, l1 = 0;
+            for (int ax = 0; ax < 3; ++ax) {
+              const int v = o[ax], w = o[ax] - (ax == dn);
+              l0 += v < 0 ? -v : v;
+              l1 += w < 0 ? -w : w;
+            }
+            if (l0 <= R || l1 <= R) {
+              off[dn][cnt][0] = (int8_t)x;
+              off[dn][cnt][1] = (int8_t)y;
+              off[dn][cnt][2] = (int8_t)z;
+              ++cnt;
+            }
+          }
+      n = cnt;
+    }
+  }
+};
+
+template <int D, int R>
+inline constexpr RegularRows<D, R> kRegularRows{};
+
 template <int D, int R, bool FILL>
 __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long n_face,
                                                    const int32_t* __restrict__ fcode, const int32_t* __restrict__ fref,
@@ -220,7 +295,7 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
                                                    const int32_t* __restrict__ eb_id, const int32_t* __restrict__ face_id,
                                                    const int32_t* __restrict__ box_id, const int64_t* __restrict__ counts,
                                                    const int64_t* __restrict__ offs, const uint8_t* __restrict__ cellinfo,
-                                                   int32_t* nrows,
+                                                   const uint8_t* __restrict__ ballreg, int32_t* nrows,
                                                    const int64_t* __restrict__ row_ptr, int32_t* col) {
   using W = Win<D, R>;
   __shared__ int8_t dist[W::NW];
@@ -232,6 +307,31 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
   const int32_t ref = fref[F];
 
   const int32_t* vid = vol_id + gi * g.ncell;
+  // fast path: a grid face between two ball-regular cells has the fixed L1-ball rows
+  if (kind == 0) {
+    int j[3];
+    lattice_coords(g, dn, ref, j);
+    if (j[dn] >= 1 && j[dn] <= g.n[dn] - 1) {
+      const long long b = cell_index(g, j);
+      const long long st[3] = {1, g.n[0], (long long)g.n[0] * g.n[1]};
+      const long long a = b - st[dn];
+      const uint8_t* reg = ballreg + (long long)gi * g.ncell;
+      if (reg[a] && reg[b]) {
+        constexpr auto& P = kRegularRows<D, R>;
+        if (!FILL) {
+          if (lane == 0) nrows[F] = P.n;
+          return;
+        }
+        const long long pos = row_ptr[F];
+        const int64_t phi0 = offs[gi];
+        for (int i = lane; i < P.n; i += 64) {
+          const long long c = a + P.off[dn][i][0] + st[1] * P.off[dn][i][1] + st[2] * P.off[dn][i][2];
+          col[pos + i] = (int32_t)(phi0 + vid[c]);
+        }
+        return;
+      }
+    }
+  }
   const int32_t* eid = eb_id + gi * g.ncell;
   const int32_t* bid = box_id + gi * g.NF;
 
@@ -264,6 +364,7 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
   unsigned open[W::K];
   unsigned info[W::K];
   int wpos[W::K][3];
+  int xk[W::K][3];      // grid coordinates of the window cells
 #pragma unroll
   for (int k = 0; k < W::K; ++k) {
     const int w = lane + 64 * k;
@@ -271,13 +372,24 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
     open[k] = 0;
     info[k] = 0;
     cell[k] = -1;
+    xk[k][0] = xk[k][1] = xk[k][2] = -1;
     if (w >= NW) continue;
-    int wc[3] = {w % ext[0], (w / ext[0]) % ext[1], w / (ext[0] * ext[1])};
+    // window coordinates with compile-time divisors (the long extent is along nrm)
+    int wc[3];
+    if (nrm == 0) {
+      wc[0] = w % W::EN; wc[1] = (w / W::EN) % W::ET; wc[2] = w / (W::EN * W::ET);
+    } else if (nrm == 1) {
+      wc[0] = w % W::ET; wc[1] = (w / W::ET) % W::EN; wc[2] = w / (W::ET * W::EN);
+    } else {
+      wc[0] = w % W::ET; wc[1] = (w / W::ET) % W::ET; wc[2] = w / (W::ET * W::ET);
+    }
+    if (D == 2) wc[2] = 0;
     int x[3];
     bool inbox = true;
     for (int ax = 0; ax < 3; ++ax) {
       wpos[k][ax] = wc[ax];
       x[ax] = org[ax] + wc[ax];
+      xk[k][ax] = x[ax];
       if (ax < D && (x[ax] < 0 || x[ax] >= g.n[ax])) inbox = false;
     }
     if (!inbox) continue;
@@ -342,8 +454,7 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
     for (int k = 0; k < W::K; ++k) {
       if (!inS[k]) continue;
       c += 1 + (int)(info[k] >> 7);
-      const long long cc = cell[k];
-      const int x[3] = {(int)(cc % g.n[0]), (int)((cc / g.n[0]) % g.n[1]), (int)(cc / ((long long)g.n[0] * g.n[1]))};
+      const int* x = xk[k];
       for (int ax = 0; ax < D; ++ax)
         for (int s = 0; s < 2; ++s)
           if (x[ax] == (s ? g.n[ax] - 1 : 0) && ((info[k] >> (1 + 2 * ax + s)) & 1u)) c += 1;   // box face
@@ -375,8 +486,7 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
       for (int k = 0; k < W::K; ++k) {
         int32_t b = -1;
         if (inS[k]) {
-          long long cc = cell[k];
-          int x[3] = {(int)(cc % g.n[0]), (int)((cc / g.n[0]) % g.n[1]), (int)(cc / ((long long)g.n[0] * g.n[1]))};
+          const int* x = xk[k];
           if (x[ax] == (s ? g.n[ax] - 1 : 0)) {
             int j[3] = {x[0], x[1], x[2]};
             j[ax] += s;
@@ -397,11 +507,11 @@ static void launch_neighbours(const Work& w, long long n_face, const int64_t* ro
   if (fill)
     hipLaunchKernelGGL((k_neighbours<D, R, true>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
                        w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
-                       w.nrows, row_ptr, col);
+                       w.ballreg, w.nrows, row_ptr, col);
   else
     hipLaunchKernelGGL((k_neighbours<D, R, false>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
                        w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
-                       w.nrows, row_ptr, col);
+                       w.ballreg, w.nrows, row_ptr, col);
 }
 
 int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const int64_t* row_ptr, int32_t* col,

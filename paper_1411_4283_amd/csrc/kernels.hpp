@@ -32,6 +32,8 @@ struct Work {
   int32_t* box_lf;      // [G][nboxslot] lattice face of each local box face
   int32_t* vol_cell;    // [G][ncell]  cell of each local volume
   uint8_t* cellinfo;    // [G][ncell]  volume / open-face / EB bits for the neighbour search
+  uint8_t* ballreg;     // [G][ncell]  1: every cell within path radius is a plain interior volume
+  uint8_t* ballreg_tmp; // [G][ncell]  erosion ping-pong buffer
   int64_t* counts;      // [G][4]      n_vol, n_eb, n_box, n_gface
   int64_t* offs;        // [3][G+1]    phi_off, vol_off, face_off
   int32_t* fcode;       // [G*maxface] per global flux face
