@@ -33,6 +33,41 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_1411_4283_amd/csrc/stencil.hip", "paper_1411_4283_amd/csrc/rows.hpp",
+                  "paper_1411_4283_amd/csrc/common.hpp", "paper_1411_4283_amd/csrc/kernels.hpp",
+                  "paper_1411_4283_amd/csrc/apply.hip")
+TRAFFIC_FILE = "profiles/traffic_3d_order4_sphere64.md"
+
+
+def sources_sha256():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per build of the stencil solves and per apply, from the rocprofv3 byte
+    counters recorded in profiles/ -- only while the kernel sources are the ones measured
+    (the summary records their SHA-256); otherwise None."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                for kv in line[len("traffic:"):].split():
+                    k, v = kv.split("=")
+                    vals[k] = v
+    if vals.get("sources_sha256") != sources_sha256():
+        return None
+    return {k: float(v) for k, v in vals.items() if k != "sources_sha256"}
+
+
 def qr_flops(N, M):
     """Householder QR of an N x M matrix (LAPACK count)."""
     return 2 * N * M * M - 2.0 / 3.0 * M**3
@@ -154,6 +189,49 @@ def batched_comparison(steps):
     return out
 
 
+def adjoint_timings(torch, cc, b, st, phi, flux, reps=5):
+    """The adjoints on the same stencils: the transpose, the apply adjoint (Phi-bar, val-bar,
+    scale-bar) and the stencil backward with a cotangent on every face.  HIP events on the
+    launch stream, median of `reps` after one warm-up."""
+    import numpy as np
+
+    s = st.sizes
+    dev = phi.device
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def transpose():
+        st.transpose = None
+        cc.build_transpose(st)
+
+    t_tr = timed(transpose)
+    lbar = torch.from_numpy(np.random.default_rng(8).standard_normal(s.n_vol)).to(dev)
+    t_adj = timed(lambda: cc.apply_adjoint(st, lbar, phi=phi, flux=flux))
+    # algorithmic bytes of the apply adjoint: the CSC (nz, nz_face) and val through it, the
+    # CSR (col, val-bar written) with Phi, face cotangents, Phi-bar, and per volume its face
+    # table, scale, lbar, flux terms and scale-bar
+    b_adj = (4 + 4 + 8) * s.nnz + (4 + 8) * s.nnz + 8 * (2 * s.n_phi + 2 * s.n_face) + (4 * 7 + 8 * 3) * s.n_vol
+    vb = torch.from_numpy(np.random.default_rng(9).standard_normal(s.nnz)).to(dev)
+    sb = torch.from_numpy(np.random.default_rng(10).standard_normal(s.n_vol)).to(dev)
+    t_bw = timed(lambda: b.backward(st, vb, sb))
+    return {"transpose_ms": t_tr, "apply_adjoint_ms": t_adj, "apply_adjoint_bytes": b_adj,
+            "apply_adjoint_gbps": b_adj / (t_adj * 1e-3) / 1e9,
+            "stencil_backward_ms": t_bw, "stencil_backward_faces_per_s": s.n_face / (t_bw * 1e-3),
+            "note": "stencil backward with a cotangent on every face (rebuilds each face's system); "
+                    "includes the per-Phi-entry moment reduction"}
+
+
 def cpu_baseline(g, R, sample, seed=7):
     """The oracle (plain FP64 numpy, one thread) on a random sample of faces: build
     (neighbours, rows, weights, stencil) plus each face's flux in the apply, and the
@@ -190,6 +268,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-geometry comparison")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoints")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one 256 MiB device copy (reference kernel for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design note, "
@@ -271,6 +352,16 @@ def main():
     achieved_tf = flops / (solve * 1e-3) / 1e12
     apply_mean = float(np.median(apply_ms))
     copy_gbs = stream_copy_gbps(torch, dev)
+    traffic = measured_traffic() if args.workload == "c3" else None
+    if args.calibrate_copy:
+        # an elementwise pass reading 256 MiB and writing 256 MiB, under a kernel name of
+        # its own (torch's negation kernel)
+        src = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     bytes_alg = 12 * s.nnz + 8 * (s.n_face + 1) + 8 * s.n_phi + 16 * s.n_vol
     apply_gbs = bytes_alg / (apply_mean * 1e-3) / 1e9
 
@@ -290,11 +381,13 @@ def main():
         "config": {"workload": w["desc"], "grid": w["n"], "order": w["Q"], "path_radius": w["R"],
                    "n_face": int(s.n_face), "nnz": int(s.nnz), "n_phi": int(s.n_phi), "n_vol": int(s.n_vol)},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / PEAK_FP64_TFLOPS,
+                     "traffic": None if traffic is None else traffic["solve_bytes_per_build"],
                      "kernel": "k_stencil (all row-count bins)", "kernel_ms": solve,
                      "flops_per_launch": flops},
         "roofline_apply": {"bound": "hbm", "achieved": apply_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                           "frac": apply_gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "k_flux + k_divergence",
+                           "frac": apply_gbs / PEAK_HBM_GBS,
+                           "traffic": None if traffic is None else traffic["apply_bytes"], "kernel": "k_flux + k_divergence",
                            "kernel_ms": apply_mean, "bytes_per_launch": bytes_alg},
         "apply_gbps": apply_gbs,
         "qr_only_tflops": flops_qr / (solve * 1e-3) / 1e12,
@@ -304,6 +397,9 @@ def main():
         "phases_ms": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
         "schedule_per_bin": schedule,
     }
+    if not args.no_adjoint:
+        log("adjoint timings")
+        out["adjoint"] = adjoint_timings(torch, cc, b, st, phi, flux)
     del st, b, dg
     torch.cuda.empty_cache()
     if not args.no_batched and args.workload == "c3":

@@ -29,6 +29,16 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr double kRankTol = 1e-7;
 constexpr int kRefine = 2;
 
+// 1/d from v_rcp_f64 and two Newton steps (each squares the relative error)
+__device__ __forceinline__ double recip_f64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+
 // One row of B = W A~ about x0 (in units of h: x0h = x0 / h) from the row's stored
 // moments m (overwritten) and centre; returns its weight in w, and false if the row
 // holds a non-finite value.
@@ -282,7 +292,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     const double sq = sqrt(d > 0.0 ? d : 0.0);
     pmax = fmax(pmax, sq);
     pmin = fmin(pmin, sq);
-    const double rd = 1.0 / d;
+    const double rd = recip_f64(d);
     const double u = (lane == k) ? 1.0 - rd : a[k] * rd;
     static_for<0, M>([&](auto J) {
       constexpr int j = J;
@@ -477,13 +487,26 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
   double sdiag;
   const int32_t* vol_cell = A.vol_cell_ws + (long long)fi.gi * A.g.ncell;
   const int32_t* box_lf = A.box_lf_ws + (long long)fi.gi * A.g.nboxslot;
-  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag);
   const bool act = lane < M;
-  const double* Bs = sm.Bs;
   const int N = fi.N;
   double* yw = B.face_yw + (long long)fi.F * 2 * M;
   double* og = B.owner_grad + (long long)fi.F * 4;
   if (lane < 4) B.face_x0[(long long)fi.F * 4 + lane] = (lane < 3) ? fi.x0h[lane] : 0.0;
+  // a face whose stencil gets no cotangent contributes nothing: skip its solve
+  bool any = false;
+  for (int r = lane; r < N; r += 64) any = any || (B.val_bar[fi.rp + r] != 0.0);
+  if (!__any(any)) {
+    for (int r = lane; r < N; r += 64) {
+      B.nz_rz[2 * (fi.rp + r)] = 0.0;
+      B.nz_rz[2 * (fi.rp + r) + 1] = 0.0;
+      if (B.weight_bar) B.weight_bar[fi.rp + r] = 0.0;
+    }
+    if (act) { yw[lane] = 0.0; yw[M + lane] = 0.0; }
+    if (lane < 4) og[lane] = 0.0;
+    return;
+  }
+  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag);
+  const double* Bs = sm.Bs;
   if (st != CUTCELL_STATUS_OK) {   // a flagged face has s = 0 whatever its inputs: no gradient
     for (int r = lane; r < N; r += 64) {
       B.nz_rz[2 * (fi.rp + r)] = 0.0;

@@ -211,3 +211,108 @@ def test_autograd_loss_gradient_matches_oracle():
         _cmp(f"face_mom[{d}]", dg.face_mom[d].grad.cpu().numpy(), G["face_mom"][d])
     _cmp("eb_mom", dg.eb_mom.grad.cpu().numpy(), G["eb_mom"])
     _cmp("eb_nmom", dg.eb_nmom.grad.cpu().numpy(), G["eb_nmom"])
+
+
+def test_sh_body_128_shape_gradient_by_finite_differences():
+    """The differentiation workload: the 128^3 unit cube minus the body
+    r = 0.3 + sum_{l<=3} c_lm Y_lm about (0.5, 0.5, 0.5), c = 0.01 * default_rng(4) N(0,1)
+    (16 coefficients), order 4, path radius 3.  Loss: l = sum over cut volumes of
+    (kappa_v (L_v(Phi) - f_v))^2 with Phi and f fixed vectors, the exact averages at c of the
+    paper's 3D solution sin 2pi(x - sqrt2/2) sin 2pi(y - sqrt3/2) sin 2pi(z - 0.54321) and of
+    its Laplacian.  The autograd gradient with respect to every moment (through the
+    hand-written adjoints), contracted with central differences of the host moments in a
+    shape coefficient, must match central differences of the loss itself.  The loss is only
+    piecewise smooth in c: a coefficient is used only if between c - h and c + h no cell
+    or face changes topology and no face's status changes.  It is also very stiff: the
+    residuals r_v = kappa_v (L_v - f_v) are ~1e-5 at c but move ~1e6 times faster than c
+    (a face flux is a sum of terms ~5e3 times larger than itself, and near-tangent cuts
+    move EB moments quickly), so the central difference of l = sum r^2 carries an error
+    sum r' r'' h^2 that swamps sum 2 r r' at h = 1e-7 (it is 1.2e-5 relative at h = 1e-9).
+    Both sides are therefore Richardson-extrapolated from h = 2e-9 and 1e-9, which removes
+    the h^2 term; the host moments' differences stay accurate to ~1e-7 at these steps."""
+    R, n, Q, hstep = 3, 128, 4, 1e-9
+    c0 = 0.01 * np.random.default_rng(4).standard_normal(16)
+    shape = lambda c: cg.sh_body_outside((0.5, 0.5, 0.5), 0.3, c)  # noqa: E731
+    g = cg.make_geometry(shape(c0), n, Q)
+    tp = 2 * np.pi
+    field = cg.trig_product((tp, tp, tp), (-tp * np.sqrt(2) / 2, -tp * np.sqrt(3) / 2, -tp * 0.54321))
+    I = g.integrate(field)
+    en = oracle.enumerate_geometry(g)
+    hD, hD1 = g.h**3, g.h**2
+    vol = en.vol_cell
+    box = np.array([I["face_int"][d][f] / (g.face_mom[d][f, 0] * hD1) for d, f in zip(en.box_dir, en.box_face)])
+    phi = np.concatenate([I["vol_int"][vol] / (g.kappa[vol] * hD), I["eb_int"] / (g.eb_mom[:, 0] * hD1), box])
+    fvol = I["vol_lap"][vol] / (g.kappa[vol] * hD)
+    cut = np.isin(vol, g.eb_cell)
+    _say(f"sh body 128^3: {en.n_face} faces, {int(cut.sum())} cut volumes")
+    phi_t = torch.from_numpy(phi).to(DEV)
+    f_t = torch.from_numpy(fvol).to(DEV)
+    cut_t = torch.from_numpy(cut).to(DEV)
+    cells_t = torch.from_numpy(vol.astype(np.int64)).to(DEV)
+
+    def loss_of(dg, keep=None):
+        op = cc.CutCellOperator(dg, R)
+        L = op(phi_t)
+        kap = dg.vol_mom[:, 0][cells_t]
+        r = torch.where(cut_t, kap * (L - f_t), torch.zeros_like(L))
+        if keep is not None:
+            keep.append(op.builder.last.status[: op.builder.last.sizes.n_face].clone())
+        return torch.sum(r * r)
+
+    dg = cc.DeviceGeometry.from_host(g, DEV)
+    leaves = [dg.vol_mom, *dg.face_mom, dg.eb_mom, dg.eb_nmom]
+    for t in leaves:
+        t.requires_grad_(True)
+    st0 = []
+    loss = loss_of(dg, st0)
+    loss.backward()
+    nflag = int((st0[0] != 0).sum())
+    torch.cuda.synchronize()
+    grads = [t.grad.cpu().numpy() for t in leaves]
+    _say(f"loss {float(loss.detach()):.6e}, {nflag} faces flagged")
+
+    def arrays(gg):
+        return [gg.vol_mom, *gg.face_mom, gg.eb_mom, gg.eb_nmom]
+
+    def same_topology(gg):
+        return (np.array_equal(gg.eb_cell, g.eb_cell) and np.array_equal(gg.kappa > 0, g.kappa > 0)
+                and all(np.array_equal(gg.face_mom[d][:, 0] > 0, g.face_mom[d][:, 0] > 0) for d in range(3)))
+
+    def central(k, hh):
+        """(adjoint contracted with the moments' central difference, central difference of
+        l) at step hh, or None when the topology or a status changes within +-hh."""
+        cp, cm = c0.copy(), c0.copy()
+        cp[k] += hh
+        cm[k] -= hh
+        gp, gm = cg.make_geometry(shape(cp), n, Q), cg.make_geometry(shape(cm), n, Q)
+        if not (same_topology(gp) and same_topology(gm)):
+            return None
+        stp, stm = [], []
+        with torch.no_grad():
+            lp = float(loss_of(cc.DeviceGeometry.from_host(gp, DEV), stp))
+            lm = float(loss_of(cc.DeviceGeometry.from_host(gm, DEV), stm))
+        if not (torch.equal(stp[0], st0[0]) and torch.equal(stm[0], st0[0])):
+            return None
+        dmu = [(x - y) / (2 * hh) for x, y in zip(arrays(gp), arrays(gm))]
+        adj = sum(float(np.sum(gr * dm)) for gr, dm in zip(grads, dmu))
+        return adj, (lp - lm) / (2 * hh)
+
+    checked = 0
+    for k in (15, 6, 13, 2, 9, 4, 11, 7, 1, 3, 5, 8, 10, 12, 14, 0):
+        if checked == 3:
+            break
+        r1 = central(k, 2 * hstep)
+        r2 = central(k, hstep) if r1 is not None else None
+        if r2 is None:
+            _say(f"coefficient {k}: topology or a status changes within the steps; not differentiable here")
+            continue
+        checked += 1
+        # Richardson: the O(h^2) terms of both central differences cancel
+        adj = (4 * r2[0] - r1[0]) / 3
+        fd = (4 * r2[1] - r1[1]) / 3
+        _say(f"coefficient {k}: h={2 * hstep:g}: adjoint {r1[0]:.10e} fd {r1[1]:.10e}; h={hstep:g}: adjoint "
+             f"{r2[0]:.10e} fd {r2[1]:.10e}")
+        _say(f"coefficient {k}: extrapolated adjoint {adj:.10e}  finite difference {fd:.10e}  "
+             f"rel {abs(adj - fd) / abs(fd):.2e}")
+        assert abs(adj - fd) <= 1e-6 * abs(fd), (k, adj, fd)
+    assert checked >= 2, "too few shape coefficients keep the topology within +-h"

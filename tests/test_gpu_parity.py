@@ -66,7 +66,12 @@ def _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g):
     return worst
 
 
-def _check_apply(g, en, st, rp, col, val, phi):
+def _check_apply(g, en, st, rp, col, val, phi, norm_check=True):
+    """L(Phi) from the GPU against the oracle's apply of the same stencils.  The per-volume
+    bound is the rounding bound of the sums (relative to the sum of the magnitudes of the
+    terms).  The norm-wise bound ||dL|| <= 1e-12 ||L|| only applies when L is not itself a
+    small difference of large fluxes (random Phi); for smooth fields L_v cancels the fluxes
+    down by 1/(kappa h^D) and only the per-volume bound is meaningful (norm_check=False)."""
     lphi, flux = cc.apply(st, torch.from_numpy(phi).to(DEV))
     torch.cuda.synchronize()
     Lg = lphi.cpu().numpy()
@@ -80,7 +85,8 @@ def _check_apply(g, en, st, rp, col, val, phi):
         np.add.at(scale, side[m], absterm[m])
     scale /= g.kappa[en.vol_cell] * g.h**g.D
     assert np.all(np.abs(Lg - L_o) <= 1e-12 * scale)
-    assert np.linalg.norm(Lg - L_o) <= 1e-12 * np.linalg.norm(L_o)
+    if norm_check:
+        assert np.linalg.norm(Lg - L_o) <= 1e-12 * np.linalg.norm(L_o)
     return Lg
 
 
@@ -283,3 +289,35 @@ def test_every_schedule_gives_identical_stencils():
     _say(f"autotuned {[(tuning.xcd_chunks[i], tuning.blocks_per_xcd[i]) for i in range(8)]} best {best}")
     assert torch.equal(st.val, val0) and torch.equal(st.status, status0)
     assert any(x > 0 for x in best)
+
+
+def test_star256_order4_full_size():
+    """The 2D fourth-order workload: the unit square minus the six-petal star
+    r(t) = 0.25 + 0.05 cos 6t about (0.5, 0.5) on 256^2 (about 106k faces), path radius 3.
+    Every face's rows are compared bit-exactly with the oracle's neighbour sets; the
+    stencils of every EB face and of 400 seeded random faces with the oracle's; and L(Phi)
+    of the seeded Fourier field (modes up to 4, default_rng(1)) with the oracle's apply of
+    the same stencils."""
+    R = 3
+    g = cg.make_geometry(cg.star2_outside((0.5, 0.5), 0.25, 0.05, 6), 256, 4)
+    dg, b, st = _gpu_build(g, R)
+    en = oracle.enumerate_geometry(g)
+    rp_g, col_g, val_g, st_g = _host(st)
+    _say(f"star256: {en.n_face} faces, nnz {len(col_g)}")
+    assert st.sizes.n_face == en.n_face and st.sizes.n_phi == en.n_phi
+    nb = [oracle.neighbours(en, f, R) for f in range(en.n_face)]
+    rp = np.zeros(en.n_face + 1, np.int64)
+    rp[1:] = np.cumsum([len(x) for x in nb])
+    assert np.array_equal(rp_g, rp)
+    assert np.array_equal(col_g, np.concatenate(nb))
+    eb_faces = np.flatnonzero(en.face_kind == S.KIND_EB)
+    faces = np.unique(np.concatenate([eb_faces, np.random.default_rng(5).choice(en.n_face, 400, replace=False)]))
+    worst = _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g)
+    _say(f"star256: {len(faces)} faces compared, worst stencil rel err {worst:.2e}")
+    field = cg.fourier_field(2, 4, np.random.default_rng(1))
+    I = g.integrate(field)
+    hD, hD1 = g.h**2, g.h
+    vol = en.vol_cell
+    box = np.array([I["face_int"][d][f] / (g.face_mom[d][f, 0] * hD1) for d, f in zip(en.box_dir, en.box_face)])
+    phi = np.concatenate([I["vol_int"][vol] / (g.kappa[vol] * hD), I["eb_int"] / (g.eb_mom[:, 0] * hD1), box])
+    _check_apply(g, en, st, rp_g, col_g, val_g, phi, norm_check=False)
