@@ -189,6 +189,34 @@ def batched_comparison(steps):
     return out
 
 
+def regular_face_count(g, R):
+    """Faces between two cells whose whole L1 ball of radius R consists of full interior
+    cells with all faces open (the neighbour search's fixed-row case); host numpy."""
+    import numpy as np
+
+    n = g.n[0]
+    vol = (g.kappa > 0).reshape(n, n, n)
+    eb = np.zeros(g.ncell, bool)
+    eb[g.eb_cell] = True
+    eb = eb.reshape(n, n, n)
+    a0 = g.face_mom[0][:, 0].reshape(n, n, n + 1)
+    a1 = g.face_mom[1][:, 0].reshape(n, n + 1, n)
+    a2 = g.face_mom[2][:, 0].reshape(n + 1, n, n)
+    opn = (a0[:, :, :-1] > 0) & (a0[:, :, 1:] > 0) & (a1[:, :-1] > 0) & (a1[:, 1:] > 0) & (a2[:-1] > 0) & (a2[1:] > 0)
+    r = vol & ~eb & opn
+    for ax in range(3):
+        idx = [slice(None)] * 3
+        for e in (0, -1):
+            idx[ax] = e
+            r[tuple(idx)] = False
+    for _ in range(R):
+        r2 = r.copy()
+        r2[1:-1, 1:-1, 1:-1] &= (r[:-2, 1:-1, 1:-1] & r[2:, 1:-1, 1:-1] & r[1:-1, :-2, 1:-1] & r[1:-1, 2:, 1:-1]
+                                 & r[1:-1, 1:-1, :-2] & r[1:-1, 1:-1, 2:])
+        r = r2
+    return int((r[:, :, :-1] & r[:, :, 1:]).sum() + (r[:, :-1] & r[:, 1:]).sum() + (r[:-1] & r[1:]).sum())
+
+
 def adjoint_timings(torch, cc, b, st, phi, flux, reps=5):
     """The adjoints on the same stencils: the transpose, the apply adjoint (Phi-bar, val-bar,
     scale-bar) and the stencil backward with a cotangent on every face.  HIP events on the
@@ -232,10 +260,31 @@ def adjoint_timings(torch, cc, b, st, phi, flux, reps=5):
                     "includes the per-Phi-entry moment reduction"}
 
 
-def cpu_baseline(g, R, sample, seed=7):
-    """The oracle (plain FP64 numpy, one thread) on a random sample of faces: build
-    (neighbours, rows, weights, stencil) plus each face's flux in the apply, and the
-    enumeration pro rata.  Returns faces/s."""
+_ORACLE_STATE = {}
+
+
+def _oracle_chunk(faces):
+    """Worker: the oracle's stencil + face flux for a list of faces (one thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    g, en, R, phi = (_ORACLE_STATE[k] for k in ("g", "en", "R", "phi"))
+    with threadpool_limits(limits=1):
+        for f in faces:
+            idx, sv, st = oracle.face_stencil(g, en, int(f), R)
+            _ = float(np.dot(sv, phi[idx]))
+    return len(faces)
+
+
+def cpu_baseline(g, R, sample, seed=7, workers=None):
+    """The oracle (plain FP64 numpy) on a random sample of faces: build (neighbours, rows,
+    weights, stencil) plus each face's flux in the apply, and the enumeration pro rata.
+    One thread, and (if `workers` > 1) the same per-face work spread over that many
+    forked worker processes.  Runs before the GPU is touched.  Returns the result dict."""
+    import multiprocessing as mp
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -245,17 +294,27 @@ def cpu_baseline(g, R, sample, seed=7):
         t0 = time.perf_counter()
         en = oracle.enumerate_geometry(g)
         t_enum = time.perf_counter() - t0
-        faces = np.random.default_rng(seed).choice(en.n_face, min(sample, en.n_face), replace=False)
-        phi = np.random.default_rng(2).standard_normal(en.n_phi)
-        t0 = time.perf_counter()
-        for f in faces:
-            idx, s, st = oracle.face_stencil(g, en, int(f), R)
-            _ = float(np.dot(s, phi[idx]))
-        t_faces = time.perf_counter() - t0
+    faces = np.random.default_rng(seed).choice(en.n_face, min(sample, en.n_face), replace=False)
+    phi = np.random.default_rng(2).standard_normal(en.n_phi)
+    _ORACLE_STATE.update(g=g, en=en, R=R, phi=phi)
+    t0 = time.perf_counter()
+    _oracle_chunk(faces)
+    t_faces = time.perf_counter() - t0
     t = t_faces + t_enum * len(faces) / en.n_face
-    return dict(value=len(faces) / t, unit="faces/s", cores=1, kind="oracle",
-                sample=f"{len(faces)} faces drawn uniformly (seed {seed}) of {en.n_face}; stencil build + "
-                       f"face flux per face, enumeration pro rata; {t:.1f} s")
+    out = dict(value=len(faces) / t, unit="faces/s", cores=1, kind="oracle",
+               sample=f"{len(faces)} faces drawn uniformly (seed {seed}) of {en.n_face}; stencil build + "
+                      f"face flux per face, enumeration pro rata; {t:.1f} s on one thread")
+    if workers and workers > 1:
+        many = np.random.default_rng(seed + 1).choice(en.n_face, min(4 * sample, en.n_face), replace=False)
+        chunks = np.array_split(many, 8 * workers)
+        with mp.get_context("fork").Pool(workers) as pool:
+            t0 = time.perf_counter()
+            done = sum(pool.map(_oracle_chunk, chunks))
+            tw = time.perf_counter() - t0
+        out["all_cores"] = dict(value=done / tw, unit="faces/s", cores=workers,
+                                sample=f"{done} faces (seed {seed + 1}) over {workers} processes, {tw:.1f} s; "
+                                       "enumeration not included")
+    return out
 
 
 def main():
@@ -278,17 +337,26 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import cutgeom as cg
-    import paper_1411_4283_amd as cc
-    from paper_1411_4283_amd import _lib
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = workload(args.workload)
     t0 = time.perf_counter()
     g = cg.make_geometry(w["shape"], w["n"], w["Q"])
     log(f"geometry {time.perf_counter() - t0:.2f} s")
+    base = None
+    if not args.no_cpu_baseline:
+        # before anything initialises the GPU: the worker processes are forks of this one
+        log("cpu baseline (oracle)")
+        base = cpu_baseline(g, w["R"], args.cpu_sample, workers=min(16, os.cpu_count() or 1))
+    regular = regular_face_count(g, w["R"]) if g.D == 3 else None
+
+    import torch
+
+    import paper_1411_4283_amd as cc
+    from paper_1411_4283_amd import _lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     dg = cc.DeviceGeometry.from_host(g, dev)
     b = cc.Builder(dg, w["R"])
@@ -396,6 +464,9 @@ def main():
         "build_faces_per_s": s.n_face / (float(np.mean([sum(v for v in p.values() if v > 0) for p in phases])) * 1e-3),
         "phases_ms": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
         "schedule_per_bin": schedule,
+        "faces_regular": regular,
+        "faces_regular_note": "faces between two cells whose whole path-radius ball is plain interior volume "
+                              "(fixed rows); every face, regular or not, is solved",
     }
     if not args.no_adjoint:
         log("adjoint timings")
@@ -405,9 +476,8 @@ def main():
     if not args.no_batched and args.workload == "c3":
         log("batched comparison (64 geometries)")
         out["batched"] = batched_comparison(max(1, min(args.steps, 3)))
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(g, w["R"], args.cpu_sample)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 
