@@ -76,17 +76,20 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 3
+#define CUTCELL_ABI_VERSION 4
 
 enum {
   CUTCELL_OK = 0,
   CUTCELL_W_FLAGGED_FACES = 1,
+  CUTCELL_W_NOT_CONVERGED = 2, /* cutcell_solve: the iteration limit came first; x holds
+                                  the last iterate                                    */
   CUTCELL_E_INVALID_ARG = -1,  /* null pointer, bad size, inconsistent sizes          */
   CUTCELL_E_UNSUPPORTED = -2,  /* D not in {2,3}, Q not in {2,4}, R_n out of [1, 4],
                                   a face with more rows than the largest kernel bin   */
   CUTCELL_E_WORKSPACE = -3,    /* workspace missing or smaller than required          */
   CUTCELL_E_HIP = -4,          /* a HIP runtime call failed (message kept)            */
-  CUTCELL_E_CAPACITY = -5      /* output arrays smaller than the sizes require        */
+  CUTCELL_E_CAPACITY = -5,     /* output arrays smaller than the sizes require        */
+  CUTCELL_E_BREAKDOWN = -6     /* cutcell_solve: the residual became non-finite        */
 };
 
 /* Per-face status (Sec. 2.2.1 asks for "sufficiently many neighbors" and a full-rank
@@ -249,6 +252,34 @@ int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const c
                               const cutcell_transpose* tr, const double* val_bar, const double* scale_bar,
                               const cutcell_geom_grad* grads, double* weight_bar, void* workspace,
                               size_t workspace_bytes, cutcell_stream_t stream);
+
+/* Bytes of workspace cutcell_solve needs for `restart` Krylov vectors (0 if restart is
+ * outside [1, 1024]).  About (restart + 8) n_vol + 2 n_phi + n_face doubles. */
+size_t cutcell_solve_workspace_bytes(const cutcell_sizes* sizes, int32_t restart);
+
+/* Solves the discrete Poisson problem L(Phi) = rhs for the volume values of Phi
+ * (Sec. 3.2; Sec. 2.2, eq. 'laplacian over V'), the EB and box entries of Phi held fixed
+ * at the Dirichlet data given in phi_bc.  L is affine in the volume values x, L = A x +
+ * L([0 | bc]); restarted GMRES(restart) with right Jacobi preconditioning (D = diag A,
+ * computed from the stencils) solves A x = rhs - L([0 | bc]).  The paper uses GMRES with
+ * an algebraic multigrid preconditioner (Sec. 3.2); this solver keeps the Krylov part
+ * and replaces the preconditioner by the diagonal.
+ *   phi_bc  [n_phi]  Phi with the boundary values; its volume entries are ignored
+ *   rhs     [n_vol]  the right-hand side per volume (the volume average of the source,
+ *                    in the units of L)
+ *   x       [n_vol]  in: the initial guess; out: the volume values of the solution
+ *   restart          Krylov vectors per cycle, 1..1024
+ *   max_iters        limit on matrix-vector products of the Arnoldi steps
+ *   rtol             stop when ||rhs - L([x | bc])||_2 <= rtol ||rhs - L([0 | bc])||_2,
+ *                    tested on the true residual
+ *   iters, relres    (host, may be NULL) iterations taken and the final relative residual
+ * Returns CUTCELL_OK, CUTCELL_W_NOT_CONVERGED, or an error.  Inner products are summed in
+ * a fixed order (512 partials per product), so the result does not vary between runs.
+ * Synchronises `stream` (every Arnoldi step reads its inner products back). */
+int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st, const double* phi_bc,
+                  const double* rhs, double* x, int32_t restart, int32_t max_iters, double rtol,
+                  void* workspace, size_t workspace_bytes, int32_t* iters, double* relres,
+                  cutcell_stream_t stream);
 
 /* Observability: when enabled (per calling thread), cutcell_build_stencils records HIP
  * events on its stream between its phases, and cutcell_last_profile copies the last

@@ -32,3 +32,4 @@ from .stencils import (  # noqa: F401
     STATUS_NONFINITE,
 )
 from .adjoint import apply_adjoint, stencils_backward  # noqa: F401,E402
+from .solve import operator_matrix, solve  # noqa: F401,E402

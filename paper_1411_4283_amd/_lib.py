@@ -86,11 +86,13 @@ class GeomGrad(ctypes.Structure):
 
 OK = 0
 W_FLAGGED_FACES = 1
+W_NOT_CONVERGED = 2
 E_INVALID_ARG = -1
 E_UNSUPPORTED = -2
 E_WORKSPACE = -3
 E_HIP = -4
 E_CAPACITY = -5
+E_BREAKDOWN = -6
 
 STATUS_OK = 0
 STATUS_INSUFFICIENT_ROWS = 1
@@ -119,6 +121,10 @@ SIGNATURES = {
                                                  ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays),
                                                  ctypes.POINTER(TransposeArrays), P, P, ctypes.POINTER(GeomGrad), P, P,
                                                  ctypes.c_size_t, P]),
+    "cutcell_solve_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes), ctypes.c_int32]),
+    "cutcell_solve": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P, P, P,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), P]),
     "cutcell_set_profiling": (None, [ctypes.c_int]),
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "cutcell_last_error": (ctypes.c_char_p, []),

@@ -13,7 +13,8 @@ from math import comb
 import torch
 
 from . import _lib
-from ._lib import Geom, GeomGrad, Opts, Sizes, StencilArrays, TransposeArrays, Tuning, check, load
+from ._lib import (OK, W_NOT_CONVERGED, Geom, GeomGrad, Opts, Sizes, StencilArrays, TransposeArrays, Tuning, check,
+                   load)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -311,6 +312,39 @@ def apply(st: Stencils, phi: torch.Tensor, lphi: torch.Tensor | None = None, flu
                               _stream(stream))
     check(rc, "cutcell_apply", allow_flagged=False)
     return lphi[: s.n_vol], flux[: s.n_face]
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor        # volume values of the solution [n_vol]
+    iters: int             # Arnoldi steps taken
+    relres: float          # final ||b - A x|| / ||b|| (true residual)
+    converged: bool
+
+
+def solve(st: Stencils, phi_bc: torch.Tensor, rhs: torch.Tensor, x0: torch.Tensor | None = None,
+          restart: int = 200, max_iters: int = 5000, rtol: float = 1e-10, stream=None) -> SolveResult:
+    """Solve L([x | bc]) = rhs for the volume values x (cutcell_solve: restarted GMRES with
+    right Jacobi preconditioning on the GPU).  `phi_bc` holds the Dirichlet values in its
+    EB and box entries; its volume entries are ignored."""
+    s = st.sizes
+    _check_f64(phi_bc, s.n_phi, "phi_bc")
+    _check_f64(rhs, s.n_vol, "rhs")
+    x = (torch.zeros(max(s.n_vol, 1), dtype=torch.float64, device=phi_bc.device) if x0 is None
+         else x0.detach().clone().contiguous())
+    _check_f64(x, s.n_vol, "x0")
+    nbytes = load().cutcell_solve_workspace_bytes(ctypes.byref(s), restart)
+    if nbytes == 0:
+        raise ValueError("restart must be in [1, 1024]")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=phi_bc.device)
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    arr = st.struct()
+    rc = load().cutcell_solve(ctypes.byref(s), st.dim, ctypes.byref(arr), _ptr(phi_bc), _ptr(rhs), _ptr(x), restart,
+                              max_iters, rtol, _ptr(ws), nbytes, ctypes.byref(it), ctypes.byref(rr), _stream(stream))
+    if rc not in (OK, W_NOT_CONVERGED):
+        check(rc, "cutcell_solve", allow_flagged=False)
+    return SolveResult(x[: s.n_vol], int(it.value), float(rr.value), rc == OK)
 
 
 def n_monomials(dim: int, order: int) -> int:

@@ -388,6 +388,34 @@ int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
                         st_->vol_scale, phi, lphi, flux, nullptr, (hipStream_t)stream);
 }
 
+size_t cutcell_solve_workspace_bytes(const cutcell_sizes* sizes, int32_t restart) {
+  if (!sizes || restart < 1 || restart > 1024 || sizes->n_vol < 0 || sizes->n_phi < 0 || sizes->n_face < 0) return 0;
+  return solve_workspace_bytes(sizes->n_vol, sizes->n_phi, sizes->n_face, restart);
+}
+
+int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const double* phi_bc,
+                  const double* rhs, double* x, int32_t restart, int32_t max_iters, double rtol, void* workspace,
+                  size_t workspace_bytes, int32_t* iters, double* relres, cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !st_->phi_off || !st_->vol_off || !phi_bc || !rhs || !x || !workspace)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (restart < 1 || restart > 1024) return fail(CUTCELL_E_INVALID_ARG, "restart must be in [1, 1024]");
+  if (max_iters < 0) return fail(CUTCELL_E_INVALID_ARG, "max_iters must be >= 0");
+  if (!(rtol >= 0.0)) return fail(CUTCELL_E_INVALID_ARG, "rtol must be >= 0");
+  if (sizes->n_geom < 1 || sizes->n_vol < 0 || sizes->n_phi >= (1LL << 31))
+    return fail(CUTCELL_E_INVALID_ARG, "bad sizes");
+  if (iters) *iters = 0;
+  if (relres) *relres = 0.0;
+  if (sizes->n_vol == 0) return CUTCELL_OK;
+  SolveOp op{dim, sizes->n_vol, sizes->n_phi, sizes->n_face, st_->row_ptr, st_->col, st_->val, st_->vol_face,
+             st_->vol_scale, (hipStream_t)stream};
+  int it = 0;
+  const int rc = solve_poisson(op, sizes->n_geom, st_->phi_off, st_->vol_off, phi_bc, rhs, x, restart, max_iters,
+                               rtol, (char*)workspace, workspace_bytes, &it, relres);
+  if (iters) *iters = it;
+  return rc;
+}
+
 size_t cutcell_transpose_workspace_bytes(const cutcell_sizes* sizes) {
   if (!sizes || sizes->nnz < 0 || sizes->nnz >= (1LL << 31)) return 0;
   return transpose_temp_bytes(sizes->nnz, sizes->n_phi);

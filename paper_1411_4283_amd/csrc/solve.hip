@@ -1,0 +1,287 @@
+// Discrete Poisson solve with the flux-divergence operator (Sec. 3.2: L(Phi) = f for the
+// volume values of Phi, the boundary rows of Phi holding Dirichlet data).
+//
+// L is affine in the volume values x:  L([x | bc]) = A x + L([0 | bc]).  Restarted GMRES(m)
+// solves A x = f - L([0 | bc]) with right Jacobi preconditioning (A D^-1 y = b, x = D^-1 y,
+// D = diag A).  Every vector operation is a kernel here; the host keeps only the small
+// Hessenberg matrix and its Givens rotations.  Orthogonalisation is classical Gram-Schmidt
+// done twice (CGS2): one batched inner-product kernel and one batched update per pass.
+// All reductions sum per-block partials in a fixed order, so a solve is deterministic.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace cutcell {
+
+constexpr int kDotBlock = 256;
+constexpr int kDotBlocks = 512;      // fixed number of partial sums per inner product
+
+static inline unsigned nb(long long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Phi index of every volume: geometry g's volumes sit at phi_off[g] + (v - vol_off[g])
+__global__ void k_vol_phi(long long n_vol, int G, const int64_t* __restrict__ phi_off,
+                          const int64_t* __restrict__ vol_off, int32_t* __restrict__ vol_phi) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= n_vol) return;
+  int lo = 0, hi = G;                // vol_off[lo] <= v < vol_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (vol_off[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  vol_phi[v] = (int32_t)(phi_off[lo] + (v - vol_off[lo]));
+}
+
+__global__ void k_scatter(long long n, const int32_t* __restrict__ idx, const double* __restrict__ x,
+                          double* __restrict__ phi) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v < n) phi[idx[v]] = x[v];
+}
+
+__global__ void k_copy(long long n, const double* __restrict__ a, double* __restrict__ b) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+// out = alpha * a + beta * b (out may alias a or b)
+__global__ void k_axpby(long long n, double alpha, const double* a, double beta, const double* b, double* out) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = alpha * a[i] + beta * b[i];
+}
+
+__global__ void k_mul(long long n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] * b[i];
+}
+
+// D^-1: A_vv = vol_scale[v] * sum over v's faces of sigma * (the face's coefficient on v)
+template <int D>
+__global__ void k_jacobi(long long n_vol, const int32_t* __restrict__ vol_face, const double* __restrict__ vol_scale,
+                         const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                         const double* __restrict__ val, const int32_t* __restrict__ vol_phi,
+                         double* __restrict__ dinv) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= n_vol) return;
+  constexpr int S = 2 * D + 1;
+  const int32_t me = vol_phi[v];
+  double s = 0.0;
+  for (int k = 0; k < S; ++k) {
+    const int32_t f = vol_face[v * S + k];
+    if (f < 0) continue;
+    const double sigma = (k < 2 * D && (k & 1) == 0) ? -1.0 : 1.0;   // low faces point into v
+    int64_t lo = row_ptr[f], hi = row_ptr[f + 1];                       // col ascending: search
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (col[mid] < me) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < row_ptr[f + 1] && col[lo] == me) s += sigma * val[lo];
+  }
+  const double a = vol_scale[v] * s;
+  dinv[v] = (a != 0.0 && isfinite(a)) ? 1.0 / a : 1.0;
+}
+
+// partial[i][b] = sum over block b's slice of V_i . w for i < k (V row-major [k][n])
+__global__ __launch_bounds__(kDotBlock) void k_mdot(long long n, int k, const double* __restrict__ V,
+                                                     const double* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double red[kDotBlock];
+  for (int i = 0; i < k; ++i) {
+    double s = 0.0;
+    for (long long t = blockIdx.x * (long long)kDotBlock + threadIdx.x; t < n; t += (long long)kDotBlocks * kDotBlock)
+      s = fma(V[i * n + t], w[t], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kDotBlock / 2; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[i * kDotBlocks + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[i] = sum of partial[i][0..kDotBlocks) in a fixed order (one block per i)
+__global__ __launch_bounds__(kDotBlock) void k_mdot_final(const double* __restrict__ partial, double* __restrict__ out) {
+  __shared__ double red[kDotBlock];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < kDotBlocks; b += kDotBlock) s += partial[i * kDotBlocks + b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kDotBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+// w -= sum_{i<k} c[i] V_i
+__global__ void k_maxpy(long long n, int k, const double* __restrict__ c, const double* __restrict__ V,
+                        double* __restrict__ w) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double s = w[t];
+  for (int i = 0; i < k; ++i) s = fma(-c[i], V[i * n + t], s);
+  w[t] = s;
+}
+
+size_t solve_workspace_bytes(long long n_vol, long long n_phi, long long n_face, int m) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t nv = std::max<long long>(n_vol, 1);
+  return al(sizeof(double) * n_phi) * 2 + al(sizeof(double) * std::max<long long>(n_face, 1)) +
+         al(sizeof(double) * nv) * 5 + al(sizeof(int32_t) * nv) + al(sizeof(double) * nv * (m + 1)) +
+         al(sizeof(double) * kDotBlocks * (m + 1)) + al(sizeof(double) * (m + 1)) * 2;
+}
+
+int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_t* vol_off, const double* phi_bc,
+                  const double* f, double* x, int m, int max_iters, double rtol, char* ws, size_t ws_bytes,
+                  int* iters_out, double* relres_out) {
+  const long long n = op.n_vol;
+  if (ws_bytes < solve_workspace_bytes(n, op.n_phi, op.n_face, m))
+    return fail(CUTCELL_E_WORKSPACE, "solve workspace too small");
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* p = ws + off; off += al(bytes); return p; };
+  const size_t nv = std::max<long long>(n, 1);
+  double* phi = (double*)take(sizeof(double) * op.n_phi);     // [x | bc]
+  double* phi0 = (double*)take(sizeof(double) * op.n_phi);    // [v | 0]
+  double* flux = (double*)take(sizeof(double) * std::max<long long>(op.n_face, 1));
+  double* b = (double*)take(sizeof(double) * nv);
+  double* w = (double*)take(sizeof(double) * nv);
+  double* z = (double*)take(sizeof(double) * nv);
+  double* dinv = (double*)take(sizeof(double) * nv);
+  double* tmp = (double*)take(sizeof(double) * nv);
+  int32_t* vphi = (int32_t*)take(sizeof(int32_t) * nv);
+  double* V = (double*)take(sizeof(double) * nv * (m + 1));
+  double* partial = (double*)take(sizeof(double) * kDotBlocks * (m + 1));
+  double* dots = (double*)take(sizeof(double) * (m + 1));
+  double* coef = (double*)take(sizeof(double) * (m + 1));
+  hipStream_t st = op.st;
+  const int T = 256;
+  const unsigned gv = nb(n, T);
+
+  auto apply = [&](const double* p, double* out) {
+    return apply_operator(op.D, op.n_face, n, op.row_ptr, op.col, op.val, op.vol_face, op.vol_scale, p, out, flux,
+                          nullptr, st);
+  };
+  // A v = L([v | 0])
+  auto matvec = [&](const double* v, double* out) {
+    hipLaunchKernelGGL(k_scatter, dim3(gv), dim3(T), 0, st, n, vphi, v, phi0);
+    return apply(phi0, out);
+  };
+  auto mdot = [&](int k, const double* vecs, const double* y, std::vector<double>& host) {
+    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(kDotBlock), 0, st, n, k, vecs, y, partial);
+    hipLaunchKernelGGL(k_mdot_final, dim3(k), dim3(kDotBlock), 0, st, partial, dots);
+    host.resize(k);
+    CC_HIP(hipMemcpyAsync(host.data(), dots, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    return (int)CUTCELL_OK;
+  };
+
+  hipLaunchKernelGGL(k_vol_phi, dim3(gv), dim3(T), 0, st, n, G, phi_off, vol_off, vphi);
+  hipLaunchKernelGGL(k_copy, dim3(nb(op.n_phi, T)), dim3(T), 0, st, op.n_phi, phi_bc, phi);
+  hipLaunchKernelGGL(k_fill_f64, dim3(nb(op.n_phi, T)), dim3(T), 0, st, phi0, op.n_phi, 0.0);
+  hipLaunchKernelGGL(k_fill_f64, dim3(gv), dim3(T), 0, st, z, n, 0.0);
+  // b = f - L([0 | bc])
+  hipLaunchKernelGGL(k_scatter, dim3(gv), dim3(T), 0, st, n, vphi, z, phi);
+  int rc = apply(phi, tmp);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0, f, -1.0, tmp, b);
+  if (op.D == 3)
+    hipLaunchKernelGGL(k_jacobi<3>, dim3(gv), dim3(T), 0, st, n, op.vol_face, op.vol_scale, op.row_ptr, op.col,
+                       op.val, vphi, dinv);
+  else
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(gv), dim3(T), 0, st, n, op.vol_face, op.vol_scale, op.row_ptr, op.col,
+                       op.val, vphi, dinv);
+  std::vector<double> hd;
+  rc = mdot(1, b, b, hd);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(hd[0]);
+  if (!std::isfinite(bnorm)) return fail(CUTCELL_E_INVALID_ARG, "non-finite right-hand side or boundary data");
+  if (bnorm == 0.0) {               // the solution is x = 0
+    hipLaunchKernelGGL(k_fill_f64, dim3(gv), dim3(T), 0, st, x, n, 0.0);
+    CC_HIP(hipStreamSynchronize(st));
+    if (iters_out) *iters_out = 0;
+    if (relres_out) *relres_out = 0.0;
+    return CUTCELL_OK;
+  }
+  int it = 0;
+  double res = bnorm;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  for (;;) {
+    // r = b - A x; the exit test always uses this true residual
+    rc = matvec(x, tmp);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0, b, -1.0, tmp, V);
+    rc = mdot(1, V, V, hd);
+    if (rc) return rc;
+    const double beta = std::sqrt(hd[0]);
+    res = beta;
+    if (!(beta > rtol * bnorm) || it >= max_iters) break;
+    hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0 / beta, V, 0.0, V, V);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    for (; j < m && it < max_iters; ++j, ++it) {
+      double* vj = V + (long long)j * n;
+      double* vn = V + (long long)(j + 1) * n;
+      hipLaunchKernelGGL(k_mul, dim3(gv), dim3(T), 0, st, n, dinv, vj, z);     // z = D^-1 v_j
+      rc = matvec(z, w);
+      if (rc) return rc;
+      std::vector<double> h(j + 1, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {            // CGS2
+        rc = mdot(j + 1, V, w, hd);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j + 1, dots, V, w);
+        for (int i = 0; i <= j; ++i) h[i] += hd[i];
+      }
+      rc = mdot(1, w, w, hd);
+      if (rc) return rc;
+      const double hn = std::sqrt(hd[0]);
+      hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, hn > 0.0 ? 1.0 / hn : 0.0, w, 0.0, w, vn);
+      // Givens rotations on column j of H
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t;
+      }
+      const double r = std::hypot(h[j], hn);
+      cs[j] = r > 0.0 ? h[j] / r : 1.0;
+      sn[j] = r > 0.0 ? hn / r : 0.0;
+      h[j] = r;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      for (int i = 0; i <= j; ++i) H[i * m + j] = h[i];
+      res = std::fabs(g[j + 1]);
+      if (res <= rtol * bnorm || hn == 0.0) {
+        ++j;
+        ++it;
+        break;
+      }
+    }
+    // y = H^-1 g (upper triangular j x j); x += D^-1 V y
+    for (int i = j - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
+      y[i] = s / H[i * m + i];
+    }
+    std::vector<double> ny(j);
+    for (int i = 0; i < j; ++i) ny[i] = -y[i];
+    CC_HIP(hipMemcpyAsync(coef, ny.data(), sizeof(double) * j, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_fill_f64, dim3(gv), dim3(T), 0, st, tmp, n, 0.0);
+    hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j, coef, V, tmp);   // tmp = V y
+    hipLaunchKernelGGL(k_mul, dim3(gv), dim3(T), 0, st, n, dinv, tmp, tmp);
+    hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0, x, 1.0, tmp, x);
+    CC_HIP(hipStreamSynchronize(st));
+  }
+  CC_HIP(hipGetLastError());
+  if (iters_out) *iters_out = it;
+  if (relres_out) *relres_out = res / bnorm;
+  if (!std::isfinite(res)) return fail(CUTCELL_E_BREAKDOWN, "GMRES produced a non-finite residual");
+  return res <= rtol * bnorm ? CUTCELL_OK : CUTCELL_W_NOT_CONVERGED;
+}
+
+}  // namespace cutcell

@@ -28,7 +28,8 @@ def test_header_declares_the_entry_points():
     names = _declared()
     for n in ("cutcell_query", "cutcell_build_stencils", "cutcell_apply", "cutcell_workspace_bytes",
               "cutcell_last_error", "cutcell_abi_version", "cutcell_stencils_backward", "cutcell_apply_adjoint",
-              "cutcell_build_transpose", "cutcell_transpose_workspace_bytes", "cutcell_backward_workspace_bytes"):
+              "cutcell_build_transpose", "cutcell_transpose_workspace_bytes", "cutcell_backward_workspace_bytes",
+              "cutcell_solve", "cutcell_solve_workspace_bytes"):
         assert n in names
 
 
@@ -39,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 3
+    assert lib.cutcell_abi_version() == 4
 
 
 def _opts(**kw):
@@ -106,3 +107,38 @@ def test_build_and_apply_reject_null_outputs(lib):
                                       None, 0, None) == _lib.E_INVALID_ARG
     assert lib.cutcell_apply(ctypes.byref(sizes), 3, ctypes.byref(st), None, None, None, None) == _lib.E_INVALID_ARG
     assert lib.cutcell_apply(ctypes.byref(sizes), 4, ctypes.byref(st), 8, 8, 8, None) == _lib.E_UNSUPPORTED
+
+
+def _fake_stencils():
+    arr = _lib.StencilArrays()
+    for name in ("row_ptr", "col", "val", "status", "vol_face", "vol_scale", "phi_off", "vol_off", "face_off"):
+        setattr(arr, name, 8)
+    return arr
+
+
+@pytest.mark.parametrize("restart,max_iters,rtol,code", [
+    (0, 10, 1e-8, _lib.E_INVALID_ARG),
+    (1025, 10, 1e-8, _lib.E_INVALID_ARG),
+    (10, -1, 1e-8, _lib.E_INVALID_ARG),
+    (10, 10, -1.0, _lib.E_INVALID_ARG),
+    (10, 10, float("nan"), _lib.E_INVALID_ARG),
+])
+def test_solve_rejects_bad_arguments_on_the_host(lib, restart, max_iters, rtol, code):
+    """Argument checks come before any device work, so these run without a GPU."""
+    sizes = _lib.Sizes(n_vol=10, n_eb=0, n_box=4, n_phi=14, n_face=20, nnz=100, max_rows=5, n_geom=1)
+    arr = _fake_stencils()
+    it = ctypes.c_int32(-1)
+    rc = lib.cutcell_solve(ctypes.byref(sizes), 2, ctypes.byref(arr), 8, 8, 8, restart, max_iters, rtol, 8, 1 << 20,
+                           ctypes.byref(it), None, None)
+    assert rc == code
+    assert lib.cutcell_last_error()
+
+
+def test_solve_workspace_size(lib):
+    sizes = _lib.Sizes(n_vol=1000, n_eb=10, n_box=40, n_phi=1050, n_face=3000, nnz=10**5, max_rows=30, n_geom=1)
+    assert lib.cutcell_solve_workspace_bytes(ctypes.byref(sizes), 0) == 0
+    assert lib.cutcell_solve_workspace_bytes(ctypes.byref(sizes), 1025) == 0
+    b10 = lib.cutcell_solve_workspace_bytes(ctypes.byref(sizes), 10)
+    b20 = lib.cutcell_solve_workspace_bytes(ctypes.byref(sizes), 20)
+    assert b10 >= 8 * (11 * 1000 + 2 * 1050 + 3000)
+    assert b20 - b10 >= 8 * 10 * 1000
