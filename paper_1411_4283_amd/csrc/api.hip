@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "solve.hpp"
 #include "scan.hpp"
 
 namespace cutcell {

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
+#include "solve.hpp"
 
 namespace cutcell {
 

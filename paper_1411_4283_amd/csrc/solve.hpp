@@ -1,0 +1,24 @@
+// The Poisson solve with the operator (Sec. 3.2).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace cutcell {
+
+// Poisson solve with the operator (Sec. 3.2): restarted, right-Jacobi-preconditioned GMRES
+struct SolveOp {
+  int D;
+  long long n_vol, n_phi, n_face;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  const int32_t* vol_face;
+  const double* vol_scale;
+  hipStream_t st;
+};
+size_t solve_workspace_bytes(long long n_vol, long long n_phi, long long n_face, int m);
+int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_t* vol_off, const double* phi_bc,
+                  const double* f, double* x, int m, int max_iters, double rtol, char* ws, size_t ws_bytes,
+                  int* iters_out, double* relres_out);
+
+}  // namespace cutcell
