@@ -21,6 +21,7 @@ from .stencils import (  # noqa: F401
     face_condition,
     face_centre,
     flux_vector,
+    eb_normal_flux,
     recentre,
     row_weights,
     volumes_within,

@@ -319,17 +319,7 @@ def flux_vector(geom, en: Enumeration, f: int, x0: np.ndarray) -> np.ndarray:
     mono = _mono(D, Q)
     F = np.zeros(len(mono))
     if en.face_kind[f] == KIND_EB:
-        e = int(en.face_lin[f])
-        c = en.row_ctr[en.n_vol + e]
-        nu = recentre(geom.eb_nmom[e], np.broadcast_to((c - x0) / en.h, (D, D)), D, Q - 1)   # [D, M1]
-        mono1 = {q: k for k, q in enumerate(_mono(D, Q - 1))}
-        for a, p in enumerate(mono):
-            for d in range(D):
-                if p[d] > 0:
-                    q = list(p)
-                    q[d] -= 1
-                    F[a] += p[d] * nu[d, mono1[tuple(q)]]
-        return F
+        return eb_normal_flux(geom, en, int(en.face_lin[f]), x0)
     d = int(en.face_dir[f])
     monof = {q: k for k, q in enumerate(_mono(D - 1, Q))}
     for a, p in enumerate(mono):
@@ -338,29 +328,66 @@ def flux_vector(geom, en: Enumeration, f: int, x0: np.ndarray) -> np.ndarray:
     return F
 
 
-def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid"):
+def eb_normal_flux(geom, en: Enumeration, e: int, x0: np.ndarray) -> np.ndarray:
+    """sum_d p_d (normal moment of exponent p - e_d, component d) of EB face e about x0,
+    scaled: the flux of each monomial xi^p through the face (Sec. 2.3), and, divided by
+    the face area, the Neumann row of eq. 'Neu moment eq for cp'.  The stored normal
+    moments, taken about the cell centre, are re-centred to x0 by the binomial theorem."""
+    D, Q = en.D, en.Q
+    mono = _mono(D, Q)
+    F = np.zeros(len(mono))
+    c = en.row_ctr[en.n_vol + e]
+    nu = recentre(geom.eb_nmom[e], np.broadcast_to((c - x0) / en.h, (D, D)), D, Q - 1)   # [D, M1]
+    mono1 = {q: k for k, q in enumerate(_mono(D, Q - 1))}
+    for a, p in enumerate(mono):
+        for d in range(D):
+            if p[d] > 0:
+                q = list(p)
+                q[d] -= 1
+                F[a] += p[d] * nu[d, mono1[tuple(q)]]
+    return F
+
+
+def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet"):
     """Rows A~ (N x M), weights W (N), flux vector F~ (M) and the Phi indices of face f.
 
     Rows follow eq. 'volume moment eq for cp' (volume averages: A_vp = m^p_v(x0)/m^0_v)
-    and eq. 'Dir moment eq for cp' (Dirichlet boundary faces: b_p = m^p(x0)/m^0; reading
-    R6: every boundary is Dirichlet); the moments about x0 come from each row's stored
-    moments by the binomial re-centring."""
+    and eq. 'Dir moment eq for cp' (Dirichlet boundary faces: b_p = m^p(x0)/m^0); the
+    moments about x0 come from each row's stored moments by the binomial re-centring.
+    With eb_bc = "neumann" the EB rows follow eq. 'Neu moment eq for cp' instead
+    (b_p = sum_d p_d m^(p-e_d)_d(x0) / m^0, the normal-derivative average; in the scaled
+    variables xi = (x - x0)/h this row is h times the physical one).  Box faces are always
+    Dirichlet."""
     idx = neighbours(en, f, R)
     x0 = face_centre(en, f, eb_x0)
     mom = en.row_mom[idx]                       # [N, M]
     delta = (en.row_ctr[idx] - x0) / en.h       # [N, D]
     A = recentre(mom, delta, en.D, en.Q) / mom[:, :1]
+    if eb_bc == "neumann":
+        for i, k in enumerate(idx):
+            if en.n_vol <= k < en.n_vol + en.n_eb:
+                e = int(k - en.n_vol)
+                A[i] = eb_normal_flux(geom, en, e, x0) / geom.eb_mom[e, 0]
+    elif eb_bc != "dirichlet":
+        raise ValueError(eb_bc)
     W = row_weights(np.sqrt(np.sum(delta * delta, axis=1)))
     F = flux_vector(geom, en, f, x0)
     return A, W, F, idx
 
 
-def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid"):
+def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet"):
     """Stencil of face f: s = h^(D-2) W (A~^T W)^+ F~ (eq. 'stencil equation solution'),
     the solution of A~^T s~ = F~ of least ||W^-1 s~|| (Sec. 2.2.1).  The pseudo-inverse
-    is applied as LAPACK's minimum-norm least-squares solve.
+    is applied as LAPACK's minimum-norm least-squares solve.  Under Neumann EB conditions
+    the values of the EB (normal-derivative) rows carry h^(D-1) instead of h^(D-2), and an
+    EB face's own flux is its prescribed data: the single entry |A_f| on its Phi entry
+    (reading: the paper does not say how the flux of a Neumann face is formed).
     Returns (Phi indices, values, status)."""
-    A, W, F, idx = face_system(geom, en, f, R, eb_x0)
+    if eb_bc == "neumann" and en.face_kind[f] == KIND_EB:
+        e = int(en.face_lin[f])
+        return (np.array([en.n_vol + e], np.int64), np.array([geom.eb_mom[e, 0] * en.h ** (en.D - 1)]),
+                STATUS_OK)
+    A, W, F, idx = face_system(geom, en, f, R, eb_x0, eb_bc)
     N, M = A.shape
     if not (np.all(np.isfinite(A)) and np.all(np.isfinite(F))):
         return idx, np.zeros(N), STATUS_NONFINITE
@@ -374,26 +401,33 @@ def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid")
     if r.min() <= RANK_TOL * r.max():
         return idx, np.zeros(N), STATUS_RANK_DEFICIENT
     y = np.linalg.lstsq(A.T * W[None, :], F, rcond=None)[0]
-    return idx, en.h ** (en.D - 2) * W * y, STATUS_OK
+    hs = np.full(N, en.h ** (en.D - 2))
+    if eb_bc == "neumann":
+        hs[(idx >= en.n_vol) & (idx < en.n_vol + en.n_eb)] *= en.h
+    return idx, hs * W * y, STATUS_OK
 
 
-def face_condition(geom, en: Enumeration, f: int, R: int) -> float:
+def face_condition(geom, en: Enumeration, f: int, R: int, eb_bc: str = "dirichlet") -> float:
     """2-norm condition number of the column-equilibrated weighted matrix W A~."""
-    A, W, F, idx = face_system(geom, en, f, R)
+    if eb_bc == "neumann" and en.face_kind[f] == KIND_EB:
+        return 1.0
+    A, W, F, idx = face_system(geom, en, f, R, eb_bc=eb_bc)
     B = W[:, None] * A
     return float(np.linalg.cond(B / np.sqrt(np.sum(B * B, axis=0))))
 
 
-def build(geom, R: int, faces=None, en: Enumeration | None = None, eb_x0: str = "centroid"):
+def build(geom, R: int, faces=None, en: Enumeration | None = None, eb_x0: str = "centroid",
+          eb_bc: str = "dirichlet"):
     """Stencils of all flux faces (or of the listed ones) as CSR arrays
-    (row_ptr int64, col int64, val float64, status int8)."""
+    (row_ptr int64, col int64, val float64, status int8); eb_bc selects Dirichlet or
+    Neumann conditions on the embedded boundary (Sec. 2.2.1; box faces stay Dirichlet)."""
     if en is None:
         en = enumerate_geometry(geom)
     fl = range(en.n_face) if faces is None else faces
     rp = [0]
     cols, vals, st = [], [], []
     for f in fl:
-        idx, s, status = face_stencil(geom, en, int(f), R, eb_x0)
+        idx, s, status = face_stencil(geom, en, int(f), R, eb_x0, eb_bc)
         cols.append(idx)
         vals.append(s)
         st.append(status)
