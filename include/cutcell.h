@@ -47,6 +47,14 @@
  *    L_v = (1/(kappa_v h^D)) sum_f sigma_vf flux_f with sigma = +1 when the face's
  *    reference normal points out of v.
  *
+ *  Boundary data (Sec. 2.2.1).  Under Dirichlet EB conditions an EB entry of Phi is the
+ *    average of phi over the face and its row is b_p = m^p(x0)/m^0 (eq. 'Dir moment eq
+ *    for cp').  Under Neumann EB conditions (cutcell_opts.eb_bc) it is the average of
+ *    grad(phi).n over the face (n out of the fluid) and its row is the normal-derivative
+ *    row b_p = sum_d p_d m^(p-e_d)_d(x0) / m^0 (eq. 'Neu moment eq for cp'), whose values
+ *    carry h^(D-1) instead of h^(D-2); the flux of a Neumann EB face is its data: its
+ *    stencil is the single entry |A_f| (physical area) on its own Phi entry.  Box faces
+ *    are Dirichlet.
  *  Memory.  Every array argument is DEVICE memory owned by the caller, except the
  *    structs themselves and cutcell_sizes, which live on the host.  The library keeps no
  *    state between calls and allocates no device memory: scratch comes from the caller's
@@ -76,7 +84,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 4
+#define CUTCELL_ABI_VERSION 5
 
 enum {
   CUTCELL_OK = 0,
@@ -127,7 +135,11 @@ typedef struct {
   int32_t path_radius;  /* R_n, 1..4 (the paper uses 2 for Q = 2 and 3 for Q = 4)      */
   const cutcell_tuning* tuning;  /* host pointer, or NULL for one workgroup per face in
                                     bin order                                          */
+  int32_t eb_bc;        /* CUTCELL_BC_DIRICHLET or CUTCELL_BC_NEUMANN on every EB face
+                           (box faces are always Dirichlet); see "Boundary data" above  */
 } cutcell_opts;
+
+enum { CUTCELL_BC_DIRICHLET = 0, CUTCELL_BC_NEUMANN = 1 };
 
 /* One geometry: device arrays in the layouts above. */
 typedef struct {
@@ -237,7 +249,8 @@ int cutcell_apply_adjoint(const cutcell_sizes* sizes, int32_t dim, const cutcell
 /* Bytes of workspace cutcell_stencils_backward needs (it includes the build's). */
 size_t cutcell_backward_workspace_bytes(const cutcell_opts* opts, const cutcell_sizes* sizes);
 
-/* Adjoint of cutcell_build_stencils (the derivative of s = W (A^T W)^+ F of Sec. 2.2.1
+/* Adjoint of cutcell_build_stencils (Dirichlet EB conditions only: CUTCELL_E_UNSUPPORTED
+ * for Neumann) (the derivative of s = W (A^T W)^+ F of Sec. 2.2.1
  * with the rows, centring and weights of Sec. 2.4): given val_bar = dl/dval [nnz] and,
  * optionally, scale_bar = dl/dvol_scale [n_vol] (from cutcell_apply_adjoint), writes
  * dl/d(inputs) into grads[g] for every geometry (overwritten, not accumulated; zero where

@@ -26,7 +26,12 @@ class Opts(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("path_radius", ctypes.c_int32),
         ("tuning", ctypes.POINTER(Tuning)),
+        ("eb_bc", ctypes.c_int32),
     ]
+
+
+BC_DIRICHLET = 0
+BC_NEUMANN = 1
 
 
 class Geom(ctypes.Structure):

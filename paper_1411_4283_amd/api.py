@@ -67,8 +67,15 @@ class DeviceGeometry:
         return s
 
 
-def make_opts(dim: int, n, h: float, order: int, path_radius: int) -> Opts:
+_BC = {"dirichlet": _lib.BC_DIRICHLET, "neumann": _lib.BC_NEUMANN}
+
+
+def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = "dirichlet") -> Opts:
+    """cutcell_opts; eb_bc: "dirichlet" or "neumann" on every embedded-boundary face."""
+    if eb_bc not in _BC:
+        raise ValueError(f"eb_bc must be one of {sorted(_BC)}")
     o = Opts()
+    o.eb_bc = _BC[eb_bc]
     o.dim = dim
     nn = list(n) + [1] * (3 - len(n))
     for d in range(3):
@@ -181,14 +188,15 @@ class Builder:
     """Holds the workspace and the ctypes structs of one batch of geometries sharing a
     grid, order and path radius, so repeated builds allocate nothing new."""
 
-    def __init__(self, geoms, path_radius: int, device="cuda"):
+    def __init__(self, geoms, path_radius: int, device="cuda", eb_bc: str = "dirichlet"):
         geoms = list(geoms) if isinstance(geoms, (list, tuple)) else [geoms]
         g0 = geoms[0]
         for g in geoms:
             assert (g.dim, g.n, g.h, g.order) == (g0.dim, g0.n, g0.h, g0.order), "a batch shares its grid"
         self.geoms = geoms
         self.dim = g0.dim
-        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius)
+        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc)
+        self.eb_bc = eb_bc
         self.garr = (Geom * len(geoms))(*[g.struct() for g in geoms])
         lib = load()
         nbytes = lib.cutcell_workspace_bytes(ctypes.byref(self.opts), len(geoms))
@@ -292,9 +300,9 @@ class Builder:
         return out, (None if wb is None else wb[: s.nnz])
 
 
-def build_stencils(geoms, path_radius: int, stream=None) -> Stencils:
+def build_stencils(geoms, path_radius: int, stream=None, eb_bc: str = "dirichlet") -> Stencils:
     """Flux stencils of every face of one geometry (or a batch sharing a grid)."""
-    return Builder(geoms, path_radius).build(stream=stream)
+    return Builder(geoms, path_radius, eb_bc=eb_bc).build(stream=stream)
 
 
 def apply(st: Stencils, phi: torch.Tensor, lphi: torch.Tensor | None = None, flux: torch.Tensor | None = None,

@@ -103,6 +103,8 @@ static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
   if (o->order != 2 && o->order != 4) return fail(CUTCELL_E_UNSUPPORTED, "order must be 2 or 4");
   if (o->path_radius < 1 || o->path_radius > 4) return fail(CUTCELL_E_UNSUPPORTED, "path_radius must be in [1, 4]");
   if (!(o->h > 0)) return fail(CUTCELL_E_INVALID_ARG, "h must be positive");
+  if (o->eb_bc != CUTCELL_BC_DIRICHLET && o->eb_bc != CUTCELL_BC_NEUMANN)
+    return fail(CUTCELL_E_INVALID_ARG, "eb_bc must be CUTCELL_BC_DIRICHLET or CUTCELL_BC_NEUMANN");
   if (o->tuning)
     for (int b = 0; b < kMaxBins; ++b)
       if (o->tuning->xcd_chunks[b] < 0 || o->tuning->xcd_chunks[b] > 64 || o->tuning->blocks_per_xcd[b] < 0 ||
@@ -462,6 +464,8 @@ int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const c
   hipStream_t st = (hipStream_t)stream;
   int rc = validate(geoms, n_geom, opts);
   if (rc) return rc;
+  if (opts->eb_bc != CUTCELL_BC_DIRICHLET)
+    return fail(CUTCELL_E_UNSUPPORTED, "the stencil adjoint supports Dirichlet EB conditions only");
   for (int i = 0; i < n_geom; ++i) {
     if (!grads[i].vol_mom) return fail(CUTCELL_E_INVALID_ARG, "grads[i].vol_mom is NULL");
     for (int d = 0; d < opts->dim; ++d)

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
                                                    const int32_t* __restrict__ box_id, const int64_t* __restrict__ counts,
                                                    const int64_t* __restrict__ offs, const uint8_t* __restrict__ cellinfo,
                                                    const uint8_t* __restrict__ ballreg, int32_t* nrows,
-                                                   const int64_t* __restrict__ row_ptr, int32_t* col) {
+                                                   const int64_t* __restrict__ row_ptr, int32_t* col, int neumann) {
   using W = Win<D, R>;
   __shared__ int8_t dist[W::NW];
   const long long F = blockIdx.x;
@@ -305,6 +305,14 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
   const int32_t code = fcode[F];
   const int gi = code >> 4, kind = (code >> 2) & 3, dn = code & 3;
   const int32_t ref = fref[F];
+  // a Neumann EB face's flux is its data: one row, its own Phi entry
+  if (kind == 1 && neumann) {
+    if (lane == 0) {
+      if (!FILL) nrows[F] = 1;
+      else col[row_ptr[F]] = (int32_t)(offs[gi] + counts[4 * gi + 0] + ref);
+    }
+    return;
+  }
 
   const int32_t* vid = vol_id + gi * g.ncell;
   // fast path: a grid face between two ball-regular cells has the fixed L1-ball rows
@@ -503,23 +511,24 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
 
 template <int D, int R>
 static void launch_neighbours(const Work& w, long long n_face, const int64_t* row_ptr, int32_t* col, bool fill,
-                              hipStream_t st) {
+                              int neumann, hipStream_t st) {
   if (fill)
     hipLaunchKernelGGL((k_neighbours<D, R, true>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
                        w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
-                       w.ballreg, w.nrows, row_ptr, col);
+                       w.ballreg, w.nrows, row_ptr, col, neumann);
   else
     hipLaunchKernelGGL((k_neighbours<D, R, false>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
                        w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
-                       w.ballreg, w.nrows, row_ptr, col);
+                       w.ballreg, w.nrows, row_ptr, col, neumann);
 }
 
 int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const int64_t* row_ptr, int32_t* col,
                    bool fill, hipStream_t st) {
   if (n_face <= 0) return CUTCELL_OK;
   const int D = o.dim, R = o.path_radius;
+  const int neumann = o.eb_bc == CUTCELL_BC_NEUMANN;
 #define CC_NB(DD, RR) \
-  if (D == DD && R == RR) { launch_neighbours<DD, RR>(w, n_face, row_ptr, col, fill, st); }
+  if (D == DD && R == RR) { launch_neighbours<DD, RR>(w, n_face, row_ptr, col, fill, neumann, st); }
   CC_NB(2, 1) CC_NB(2, 2) CC_NB(2, 3) CC_NB(2, 4) CC_NB(3, 1) CC_NB(3, 2) CC_NB(3, 3) CC_NB(3, 4)
 #undef CC_NB
   CC_HIP(hipGetLastError());

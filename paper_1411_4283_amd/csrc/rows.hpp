@@ -39,6 +39,7 @@ struct RowSource {
   int dd;           // box faces: direction of the face; -1 for volumes and EB faces
   long long loc;    // box faces: index in the direction's lattice
   int32_t cell;     // volumes and EB faces: the cell
+  int32_t eb;       // EB faces: the EB index; -1 otherwise
 };
 
 template <int D, int Q>
@@ -53,10 +54,12 @@ __device__ __forceinline__ RowSource row_source(const GridDims& g, const GeomPtr
     if (phi_local < n_vol) {
       c = vol_cell[phi_local];
       rs.src = gp.vol_mom + (long long)c * M;
+      rs.eb = -1;
     } else {
       const int64_t e = phi_local - n_vol;
       c = gp.eb_cell[e];
       rs.src = gp.eb_mom + e * M;
+      rs.eb = (int32_t)e;
     }
     const int ci[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
     for (int ax = 0; ax < D; ++ax) rs.ctr[ax] = ci[ax] + 0.5;
@@ -74,6 +77,7 @@ __device__ __forceinline__ RowSource row_source(const GridDims& g, const GeomPtr
     rs.dd = dd;
     rs.loc = loc;
     rs.cell = -1;
+    rs.eb = -1;
   }
   return rs;
 }

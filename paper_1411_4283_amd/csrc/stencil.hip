@@ -15,6 +15,10 @@
 //      refinement with the residual F~ - B^T z computed from B itself, which brings the
 //      error down to that of a backward-stable solve (cond(B) * eps);
 //   5. val = h^(D-2) W z.
+// Under Neumann EB conditions (a separate kernel instance) the EB rows are the
+// normal-derivative rows of eq. 'Neu moment eq for cp' and their values carry h^(D-1);
+// the EB faces themselves have a one-entry stencil (their area) and are written by
+// k_insufficient, the kernel of faces with fewer rows than monomials.
 // Status: fewer rows than monomials, a pivot square root below 1e-7 times the largest after
 // equilibration (numerically rank deficient), or a non-finite entry flag the face.
 #include <algorithm>
@@ -55,6 +59,45 @@ __device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h,
   const double mu0 = m[0];
   recentre<D, Q>(m, delta);
   const double sc = w / mu0;
+  bool finite = isfinite(sc);
+  static_for<0, M>([&](auto I) {
+    m[I] *= sc;
+    finite = finite && isfinite(m[I]);
+  });
+  return finite;
+}
+
+// Neumann row of EB face e about x0 (eq. 'Neu moment eq for cp'): the flux of each
+// monomial xi^p through the face, sum_d p_d nu_d^(p - e_d)(x0), over the face area m^0,
+// times the row's weight.  The normal moments are stored about the cut cell's centre
+// `ctr` and re-centred to x0 like the other rows.  Returns false on a non-finite value.
+template <int D, int Q>
+__device__ __forceinline__ bool neumann_row(const GeomPtrs& gp, int32_t e, const double* ctr, const double* x0h,
+                                            double* m, double& w) {
+  constexpr int M = Dims<D, Q>::M, M1 = Dims<D, Q>::M1;
+  double delta[3] = {0, 0, 0};
+  double d2 = 0;
+  for (int ax = 0; ax < D; ++ax) {
+    delta[ax] = ctr[ax] - x0h[ax];
+    d2 += delta[ax] * delta[ax];
+  }
+  w = row_weight(d2);
+  const double sc = w / gp.eb_mom[(long long)e * M];
+  static_for<0, M>([&](auto I) { m[I] = 0.0; });
+  static_for<0, D>([&](auto AX) {
+    double nu[M1];
+    const double* src = gp.eb_nmom + ((long long)e * D + AX) * M1;
+    static_for<0, M1>([&](auto I) { nu[I] = src[I]; });
+    recentre<D, Q - 1>(nu, delta);
+    static_for<0, M>([&](auto I) {
+      constexpr int pd = kMono<D, Q>.e[I][AX];
+      if constexpr (pd > 0) {
+        constexpr int j = mono_index<D>(kMono<D, Q>.e[I][0] - (AX == 0), kMono<D, Q>.e[I][1] - (AX == 1),
+                                        kMono<D, Q>.e[I][2] - (AX == 2));
+        m[I] = fma((double)pd, nu[j], m[I]);
+      }
+    });
+  });
   bool finite = isfinite(sc);
   static_for<0, M>([&](auto I) {
     m[I] *= sc;
@@ -170,7 +213,7 @@ __device__ __forceinline__ void face_flux(const GridDims& g, const GeomPtrs& gp,
 // Rows, Gram matrix, inverse and the refined semi-normal solve of one face.  Leaves B, W,
 // z and y in shared memory and -G^^-1 (row `lane`) in a[], the column
 // equilibration in sdiag.  Returns the face status.
-template <int D, int Q, int NPAD>
+template <int D, int Q, int NPAD, bool NEU = false>
 __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
                                             const int32_t* __restrict__ vol_cell, const int32_t* __restrict__ box_lf,
                                             const int32_t* __restrict__ col, FaceSmem<D, Q, NPAD>& sm, int lane,
@@ -198,8 +241,17 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       double m[M];
       double wr = 0.0;
       if (r < N) {
-        load_row_moments<D, Q>(rsrc[R], m);
-        finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr) && finite;
+        if constexpr (NEU) {
+          if (rsrc[R].eb >= 0) {
+            finite = neumann_row<D, Q>(gp, rsrc[R].eb, rsrc[R].ctr, fi.x0h, m, wr) && finite;
+          } else {
+            load_row_moments<D, Q>(rsrc[R], m);
+            finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr) && finite;
+          }
+        } else {
+          load_row_moments<D, Q>(rsrc[R], m);
+          finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr) && finite;
+        }
       } else {
         static_for<0, M>([&](auto I) { m[I] = 0.0; });
       }
@@ -378,6 +430,7 @@ struct StencilArgs {
   // XCDs in turn) and walks that XCD's contiguous chunk of the bin with stride per_xcd
   int xcd;
   int per_xcd;
+  double h;            // grid spacing (Neumann rows carry one more power of h)
 };
 
 // Faces of a bin taken by workgroup blockIdx.x in turn (-1 when done).  With xcd = 1 and a
@@ -419,7 +472,7 @@ __device__ __forceinline__ FaceInfo face_info(const StencilArgs& A, long long t)
 // One face per workgroup (WALK = false: face t of the bin, t from the XCD mapping), or a
 // persistent workgroup that walks its chunk (WALK = true).  Two instances because the
 // loop costs the single-face kernel registers.
-template <int D, int Q, int NPAD>
+template <int D, int Q, int NPAD, bool NEU>
 __device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, FaceSmem<D, Q, NPAD>& sm, int lane,
                                              double* __restrict__ val, int8_t* __restrict__ status, int32_t* flagged) {
   constexpr int M = Dims<D, Q>::M;
@@ -428,17 +481,24 @@ __device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, 
   face_x0<D, Q>(A.g, gp, fi);
   double a[M];
   double sdiag;
-  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
-                                          A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a, sdiag);
-  for (int r = lane; r < fi.N; r += 64)
-    val[fi.rp + r] = (st == CUTCELL_STATUS_OK) ? A.hscale * sm.wls[r] * sm.zs[r] : 0.0;
+  const int st = face_forward<D, Q, NPAD, NEU>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
+                                               A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a,
+                                               sdiag);
+  for (int r = lane; r < fi.N; r += 64) {
+    double v = (st == CUTCELL_STATUS_OK) ? A.hscale * sm.wls[r] * sm.zs[r] : 0.0;
+    if constexpr (NEU) {
+      const int64_t k = (int64_t)A.col[fi.rp + r] - fi.phi0;
+      if (k >= fi.n_vol && k < fi.n_vol + fi.n_eb) v *= A.h;
+    }
+    val[fi.rp + r] = v;
+  }
   if (lane == 0) {
     status[fi.F] = (int8_t)st;
     if (st != CUTCELL_STATUS_OK) atomicAdd(flagged, 1);
   }
 }
 
-template <int D, int Q, int NPAD, bool WALK>
+template <int D, int Q, int NPAD, bool WALK, bool NEU = false>
 __global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restrict__ val, int8_t* __restrict__ status,
                                                int32_t* flagged) {
   __shared__ FaceSmem<D, Q, NPAD> sm;
@@ -446,10 +506,10 @@ __global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restric
   FaceWalk walk(A);
   if constexpr (!WALK) {
     const long long t = walk.next();
-    if (t >= 0 && t < A.nbin) stencil_face<D, Q, NPAD>(A, t, sm, lane, val, status, flagged);
+    if (t >= 0 && t < A.nbin) stencil_face<D, Q, NPAD, NEU>(A, t, sm, lane, val, status, flagged);
   } else {
     for (long long t = walk.next(); t >= 0 && t < A.nbin; t = walk.next()) {
-      stencil_face<D, Q, NPAD>(A, t, sm, lane, val, status, flagged);
+      stencil_face<D, Q, NPAD, NEU>(A, t, sm, lane, val, status, flagged);
       __syncthreads();   // the next face reuses the shared memory
     }
   }
@@ -673,12 +733,25 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
   }
 }
 
-// faces with fewer rows than monomials: zero stencil, status INSUFFICIENT_ROWS
+// Faces with fewer rows than monomials: zero stencil, status INSUFFICIENT_ROWS -- except,
+// under Neumann EB conditions, the EB faces, whose one-row stencil is their area
+// |A_f| = h^(D-1) m^0 (the flux is the prescribed data).
 __global__ void k_insufficient(const int32_t* __restrict__ perm, long long n, const int64_t* __restrict__ row_ptr,
-                               double* val, int8_t* status, int32_t* flagged) {
+                               double* val, int8_t* status, int32_t* flagged, const int32_t* __restrict__ fcode,
+                               const int32_t* __restrict__ fref, const GeomPtrs* __restrict__ geoms, int neumann,
+                               double hd1, int M) {
   long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int32_t F = perm[t];
+  const int32_t code = fcode[F];
+  if (neumann && ((code >> 2) & 3) == 1) {
+    const double area = hd1 * geoms[code >> 4].eb_mom[(long long)fref[F] * M];
+    const bool ok = isfinite(area);
+    val[row_ptr[F]] = ok ? area : 0.0;
+    status[F] = ok ? CUTCELL_STATUS_OK : CUTCELL_STATUS_NONFINITE;
+    if (!ok) atomicAdd(flagged, 1);
+    return;
+  }
   for (int64_t j = row_ptr[F]; j < row_ptr[F + 1]; ++j) val[j] = 0.0;
   status[F] = CUTCELL_STATUS_INSUFFICIENT_ROWS;
   atomicAdd(flagged, 1);
@@ -703,6 +776,7 @@ static StencilArgs stencil_args(const Work& w, double hscale, const int32_t* per
   A.box_lf_ws = w.box_lf;
   A.row_ptr = row_ptr;
   A.col = col;
+  A.h = 0.0;
   return A;
 }
 
@@ -734,7 +808,7 @@ struct BinSchedule {
 template <int D, int Q, int NPAD>
 static void launch_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, const int64_t* row_ptr,
                        const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
-                       BinSchedule sc) {
+                       BinSchedule sc, bool neu, double h) {
   if (nbin <= 0) return;
   StencilArgs A = stencil_args(w, hscale, perm, nbin, row_ptr, col);
   if (bw) {
@@ -746,6 +820,13 @@ static void launch_bin(const Work& w, double hscale, const int32_t* perm, long l
   const long long per = sc.per_xcd > 0 ? std::min<long long>(sc.per_xcd, chunk) : chunk;
   A.xcd = X;
   A.per_xcd = (int)per;
+  if (neu) {   // one workgroup per face (no persistent instance of the Neumann kernel)
+    A.per_xcd = (int)chunk;
+    A.h = h;
+    hipLaunchKernelGGL((k_stencil<D, Q, NPAD, false, true>), dim3((unsigned)(X * chunk)), dim3(64), 0, st, A, val,
+                       status, w.flagged);
+    return;
+  }
   if (per < chunk)
     hipLaunchKernelGGL((k_stencil<D, Q, NPAD, true>), dim3((unsigned)(X * per)), dim3(64), 0, st, A, val, status,
                        w.flagged);
@@ -757,7 +838,7 @@ static void launch_bin(const Work& w, double hscale, const int32_t* perm, long l
 template <int D, int Q>
 static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count, const int64_t* row_ptr,
                          const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
-                         const BinSchedule* sched, int only_bin) {
+                         const BinSchedule* sched, int only_bin, bool neu, double h) {
   constexpr int M = binom(Q + D, D);
   long long start = 0;
   for (int b = 0; b < kMaxBins; ++b) {
@@ -768,14 +849,14 @@ static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count,
     const int npad = kBinRows * (b + 1);
     if (npad < M) return fail(CUTCELL_E_INVALID_ARG, "internal: face with N >= M in a bin narrower than M");
     switch (npad) {
-      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
-      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b]); break;
+      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
     }
   }
   const long long ninsuf = (only_bin < 0) ? bin_count[kMaxBins] : 0;
@@ -784,7 +865,8 @@ static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count,
                        w.perm + start, ninsuf, row_ptr, (int)M, *bw);
   else if (ninsuf > 0)
     hipLaunchKernelGGL(k_insufficient, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st, w.perm + start,
-                       ninsuf, row_ptr, val, status, w.flagged);
+                       ninsuf, row_ptr, val, status, w.flagged, w.fcode, w.fref, w.geoms, (int)neu,
+                       D == 3 ? h * h : h, (int)M);
   CC_HIP(hipGetLastError());
   return CUTCELL_OK;
 }
@@ -796,7 +878,8 @@ static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_cou
   for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
 #define CC_RB(DD, QQ) \
   if (o.dim == DD && o.order == QQ) \
-    return dispatch_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin);
+    return dispatch_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin, \
+                                 o.eb_bc == CUTCELL_BC_NEUMANN, o.h);
   CC_RB(2, 2) CC_RB(2, 4) CC_RB(3, 2) CC_RB(3, 4)
 #undef CC_RB
   return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 4
+    assert lib.cutcell_abi_version() == 5
 
 
 def _opts(**kw):
@@ -142,3 +142,38 @@ def test_solve_workspace_size(lib):
     b20 = lib.cutcell_solve_workspace_bytes(ctypes.byref(sizes), 20)
     assert b10 >= 8 * (11 * 1000 + 2 * 1050 + 3000)
     assert b20 - b10 >= 8 * 10 * 1000
+
+
+def test_bad_boundary_condition_rejected(lib):
+    o = _opts()
+    o.eb_bc = 2
+    g = _lib.Geom()
+    g.vol_mom = 8
+    for d in range(3):
+        g.face_mom[d] = 8
+    sizes = _lib.Sizes()
+    rc = lib.cutcell_query(ctypes.byref(g), 1, ctypes.byref(o), None, 0, ctypes.byref(sizes), None)
+    assert rc == _lib.E_INVALID_ARG
+    assert b"eb_bc" in lib.cutcell_last_error()
+
+
+def test_stencil_adjoint_rejects_neumann_on_the_host(lib):
+    """The adjoint supports Dirichlet EB conditions only; the check precedes device work."""
+    o = _opts()
+    o.eb_bc = _lib.BC_NEUMANN
+    g = _lib.Geom()
+    g.vol_mom = 8
+    for d in range(3):
+        g.face_mom[d] = 8
+    sizes = _lib.Sizes(n_vol=10, n_eb=0, n_box=4, n_phi=14, n_face=20, nnz=100, max_rows=5, n_geom=1)
+    arr = _fake_stencils()
+    tr = _lib.TransposeArrays()
+    tr.col_ptr, tr.nz, tr.nz_face = 8, 8, 8
+    gr = _lib.GeomGrad()
+    gr.vol_mom = 8
+    for d in range(3):
+        gr.face_mom[d] = 8
+    rc = lib.cutcell_stencils_backward(ctypes.byref(g), 1, ctypes.byref(o), ctypes.byref(sizes), ctypes.byref(arr),
+                                       ctypes.byref(tr), 8, None, ctypes.byref(gr), None, 8, 1 << 20, None)
+    assert rc == _lib.E_UNSUPPORTED
+    assert b"Dirichlet" in lib.cutcell_last_error()
