@@ -263,6 +263,74 @@ def adjoint_timings(torch, cc, b, st, phi, flux, reps=5):
 _ORACLE_STATE = {}
 
 
+def reuse_timings(torch, cc, dg, R, tuning, st_full, steps, n_face, full_ms):
+    """The build with template reuse (faces whose systems are bitwise identical copy one
+    solved face's stencil), same schedule, timed like the main step; its output is
+    compared with the full build bit for bit.  Reported beside the headline, which solves
+    every face as the paper does."""
+    from paper_1411_4283_amd import _lib
+
+    br = cc.Builder(dg, R, reuse_templates=True)
+    br.set_tuning(tuning)
+    br.query()
+    sr = br.allocate()
+    for _ in range(2):
+        br.build(out=sr)
+    torch.cuda.synchronize()
+    _lib.set_profiling(True)
+    solve = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        br.build(out=sr)
+        solve.append(_lib.last_profile()["solve"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _lib.set_profiling(False)
+    ms = (t1 - t0) / steps * 1e3
+    same = all(torch.equal(getattr(sr, k), getattr(st_full, k)) for k in ("row_ptr", "col", "val", "status"))
+    return {"ms_per_step": ms, "faces_per_s": n_face / (ms * 1e-3), "speedup_vs_full_build": full_ms / ms,
+            "solve_ms": sum(solve) / len(solve), "faces_copied": int(sr.reused), "faces_solved": int(n_face - sr.reused),
+            "bitwise_equal_to_full_build": bool(same)}
+
+
+def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200):
+    """The discrete Poisson problem on the workload's geometry (Dirichlet data and source
+    from the paper's 3D exact solution, Sec. 3.6) solved by the GPU GMRES (cutcell_solve);
+    wall-clock time of the call, iterations, and the solution error against the exact
+    volume averages."""
+    import numpy as np
+
+    import cutgeom as cg
+
+    tp = 2 * math.pi
+    I = g.integrate(cg.trig_product((tp,) * g.D, (-tp * math.sqrt(2) / 2, -tp * math.sqrt(3) / 2, -tp * 0.54321)[: g.D]))
+    hD, hD1 = g.h**g.D, g.h ** (g.D - 1)
+    kap = g.kappa
+    vol_avg = np.divide(I["vol_int"], kap * hD, out=np.zeros_like(kap), where=kap > 0)
+    eb_avg = I["eb_int"] / (g.eb_mom[:, 0] * hD1)
+    face_avg = [np.divide(I["face_int"][d], g.alpha(d) * hD1, out=np.zeros(len(g.alpha(d))), where=g.alpha(d) > 0)
+                for d in range(g.D)]
+    phi = g.layout_phi(vol_avg, eb_avg, face_avg)
+    vols = np.nonzero(kap > 0)[0]
+    rhs = I["vol_lap"][vols] / (kap[vols] * hD)
+    dev = st.val.device
+    phi_t = torch.from_numpy(phi).to(dev)
+    rhs_t = torch.from_numpy(rhs).to(dev)
+    cc.solve(st, phi_t, rhs_t, rtol=rtol, restart=restart, max_iters=5)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = cc.solve(st, phi_t, rhs_t, rtol=rtol, restart=restart, max_iters=20000)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    e = res.x.cpu().numpy() - phi[: len(vols)]
+    V = kap[vols] * hD
+    return {"ms": ms, "iterations": res.iters, "ms_per_iteration": ms / max(res.iters, 1), "relres": res.relres,
+            "converged": res.converged, "rtol": rtol, "restart": restart,
+            "apply_share": res.iters * apply_ms / ms, "n_vol": int(len(vols)),
+            "error_Linf": float(np.abs(e).max()), "error_L1": float(np.sum(np.abs(e) * V) / V.sum()),
+            "preconditioner": "Jacobi (right)"}
+
+
 def _oracle_chunk(faces):
     """Worker: the oracle's stencil + face flux for a list of faces (one thread)."""
     import numpy as np
@@ -328,6 +396,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-geometry comparison")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoints")
+    ap.add_argument("--no-reuse", action="store_true", help="skip timing the template-reuse build")
+    ap.add_argument("--no-solve", action="store_true", help="skip timing the GPU Poisson solve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 256 MiB device copy (reference kernel for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -471,6 +541,12 @@ def main():
     if not args.no_adjoint:
         log("adjoint timings")
         out["adjoint"] = adjoint_timings(torch, cc, b, st, phi, flux)
+    if not args.no_reuse:
+        log("template reuse")
+        out["template_reuse"] = reuse_timings(torch, cc, dg, w["R"], b.tuning, st, args.steps, s.n_face, ms_per_step)
+    if not args.no_solve:
+        log("Poisson solve")
+        out["poisson_solve"] = solve_timings(torch, cc, g, st, apply_mean)
     del st, b, dg
     torch.cuda.empty_cache()
     if not args.no_batched and args.workload == "c3":

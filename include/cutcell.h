@@ -84,7 +84,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 5
+#define CUTCELL_ABI_VERSION 6
 
 enum {
   CUTCELL_OK = 0,
@@ -137,6 +137,14 @@ typedef struct {
                                     bin order                                          */
   int32_t eb_bc;        /* CUTCELL_BC_DIRICHLET or CUTCELL_BC_NEUMANN on every EB face
                            (box faces are always Dirichlet); see "Boundary data" above  */
+  int32_t reuse_templates; /* 1: solve one face per (geometry, direction) among the faces
+                           whose systems are bitwise identical -- grid faces whose cells
+                           within the path radius (plus one) are plain interior volumes
+                           carrying, with their faces, exactly the moments of a reference
+                           cell -- and copy its stencil to the others.  The output is bit
+                           for bit that of a build without reuse; only the work differs
+                           (cutcell_last_reused_faces counts the copies).  0: solve every
+                           face, as the paper does.                                     */
 } cutcell_opts;
 
 enum { CUTCELL_BC_DIRICHLET = 0, CUTCELL_BC_NEUMANN = 1 };
@@ -301,6 +309,10 @@ int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
  * not run).  Returns the number of phases (6), or CUTCELL_E_INVALID_ARG. */
 void cutcell_set_profiling(int enable);
 int cutcell_last_profile(double* ms, int32_t n);
+
+/* Faces whose stencil the last build on the calling thread copied from a template
+ * (cutcell_opts.reuse_templates), 0 without reuse. */
+int64_t cutcell_last_reused_faces(void);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* cutcell_last_error(void);

@@ -27,6 +27,7 @@ class Opts(ctypes.Structure):
         ("path_radius", ctypes.c_int32),
         ("tuning", ctypes.POINTER(Tuning)),
         ("eb_bc", ctypes.c_int32),
+        ("reuse_templates", ctypes.c_int32),
     ]
 
 
@@ -132,6 +133,7 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), P]),
     "cutcell_set_profiling": (None, [ctypes.c_int]),
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
+    "cutcell_last_reused_faces": (ctypes.c_int64, []),
     "cutcell_last_error": (ctypes.c_char_p, []),
     "cutcell_abi_version": (ctypes.c_int, []),
 }

@@ -70,12 +70,15 @@ class DeviceGeometry:
 _BC = {"dirichlet": _lib.BC_DIRICHLET, "neumann": _lib.BC_NEUMANN}
 
 
-def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = "dirichlet") -> Opts:
-    """cutcell_opts; eb_bc: "dirichlet" or "neumann" on every embedded-boundary face."""
+def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = "dirichlet",
+              reuse_templates: bool = False) -> Opts:
+    """cutcell_opts; eb_bc: "dirichlet" or "neumann" on every embedded-boundary face;
+    reuse_templates: copy the stencils of faces whose systems are bitwise identical."""
     if eb_bc not in _BC:
         raise ValueError(f"eb_bc must be one of {sorted(_BC)}")
     o = Opts()
     o.eb_bc = _BC[eb_bc]
+    o.reuse_templates = 1 if reuse_templates else 0
     o.dim = dim
     nn = list(n) + [1] * (3 - len(n))
     for d in range(3):
@@ -102,6 +105,7 @@ class Stencils:
     vol_off: torch.Tensor
     face_off: torch.Tensor
     code: int = 0
+    reused: int = 0            # faces whose stencil was copied from a template
     transpose: "Transpose | None" = None
     _keep: list = field(default_factory=list, repr=False)
 
@@ -188,14 +192,15 @@ class Builder:
     """Holds the workspace and the ctypes structs of one batch of geometries sharing a
     grid, order and path radius, so repeated builds allocate nothing new."""
 
-    def __init__(self, geoms, path_radius: int, device="cuda", eb_bc: str = "dirichlet"):
+    def __init__(self, geoms, path_radius: int, device="cuda", eb_bc: str = "dirichlet",
+                 reuse_templates: bool = False):
         geoms = list(geoms) if isinstance(geoms, (list, tuple)) else [geoms]
         g0 = geoms[0]
         for g in geoms:
             assert (g.dim, g.n, g.h, g.order) == (g0.dim, g0.n, g0.h, g0.order), "a batch shares its grid"
         self.geoms = geoms
         self.dim = g0.dim
-        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc)
+        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc, reuse_templates)
         self.eb_bc = eb_bc
         self.garr = (Geom * len(geoms))(*[g.struct() for g in geoms])
         lib = load()
@@ -262,6 +267,7 @@ class Builder:
                                            ctypes.byref(self.sizes), ctypes.byref(arr), _ptr(self.workspace),
                                            self.workspace.numel(), _stream(stream))
         out.code = check(rc, "cutcell_build_stencils")
+        out.reused = int(load().cutcell_last_reused_faces())
         return out
 
 

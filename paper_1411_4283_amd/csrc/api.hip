@@ -16,6 +16,7 @@ static thread_local std::string g_last_error;
 constexpr int kPhases = 6;   // enumerate, count+scan, fill, bin, solve, tables
 static thread_local bool g_profiling = false;
 static thread_local double g_phase_ms[kPhases] = {-1, -1, -1, -1, -1, -1};
+static thread_local int64_t g_last_reused = 0;
 
 struct PhaseTimer {
   hipEvent_t ev[kPhases + 1];
@@ -81,6 +82,10 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   t.cellinfo = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
   t.ballreg = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
   t.ballreg_tmp = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
+  t.canon = (uint8_t*)take(sizeof(uint8_t) * G * g.ncell);
+  t.ref_cell = (int32_t*)take(sizeof(int32_t) * G);
+  t.tface = (int32_t*)take(sizeof(int32_t) * 3 * G);
+  t.tmpl = (int32_t*)take(sizeof(int32_t) * totface);
   t.counts = (int64_t*)take(sizeof(int64_t) * 4 * G);
   t.offs = (int64_t*)take(sizeof(int64_t) * 3 * (G + 1));
   t.fcode = (int32_t*)take(sizeof(int32_t) * totface);
@@ -103,6 +108,8 @@ static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
   if (o->order != 2 && o->order != 4) return fail(CUTCELL_E_UNSUPPORTED, "order must be 2 or 4");
   if (o->path_radius < 1 || o->path_radius > 4) return fail(CUTCELL_E_UNSUPPORTED, "path_radius must be in [1, 4]");
   if (!(o->h > 0)) return fail(CUTCELL_E_INVALID_ARG, "h must be positive");
+  if (o->reuse_templates != 0 && o->reuse_templates != 1)
+    return fail(CUTCELL_E_INVALID_ARG, "reuse_templates must be 0 or 1");
   if (o->eb_bc != CUTCELL_BC_DIRICHLET && o->eb_bc != CUTCELL_BC_NEUMANN)
     return fail(CUTCELL_E_INVALID_ARG, "eb_bc must be CUTCELL_BC_DIRICHLET or CUTCELL_BC_NEUMANN");
   if (o->tuning)
@@ -325,12 +332,17 @@ static int build_common(const cutcell_geom* geoms, int32_t n_geom, const cutcell
   if (rc) return rc;
   timer.mark();
   const int M = binom(opts->order + opts->dim, opts->dim);
-  rc = bin_faces(w, P.n_face, M, st);
+  if (opts->reuse_templates) {
+    rc = find_templates(w, *opts, P.n_face, st);
+    if (rc) return rc;
+  }
+  rc = bin_faces(w, P.n_face, M, opts->reuse_templates ? w.tmpl : nullptr, st);
   if (rc) return rc;
   timer.mark();
   int32_t bc[kBinWords];
   CC_HIP(hipMemcpyAsync(bc, w.bins, sizeof(bc), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
+  g_last_reused = bc[kMaxBins + 1];
   if (tune_out) {
     double bm[kMaxBins];
     rc = tune_stencils(w, *opts, bc, out->row_ptr, out->col, out->val, out->status, st, tune_out, reps, bm);
@@ -374,6 +386,8 @@ int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_op
 }
 
 void cutcell_set_profiling(int enable) { g_profiling = enable != 0; }
+
+int64_t cutcell_last_reused_faces(void) { return g_last_reused; }
 
 int cutcell_last_profile(double* ms, int32_t n) {
   if (!ms || n < 0) return fail(CUTCELL_E_INVALID_ARG, "ms is NULL");
@@ -509,7 +523,7 @@ int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const c
   if (rc) return rc;
   rc = max_rows(w, P.n_face, st);
   if (rc) return rc;
-  rc = bin_faces(w, P.n_face, M, st);
+  rc = bin_faces(w, P.n_face, M, nullptr, st);
   if (rc) return rc;
   int32_t bc[kBinWords];
   CC_HIP(hipMemcpyAsync(bc, w.bins, sizeof(bc), hipMemcpyDeviceToHost, st));

@@ -581,17 +581,19 @@ int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, i
 // faces with fewer rows than monomials; perm lists faces bucket by bucket
 
 // per-block histograms in LDS, one global atomic per bucket per block
+__device__ __forceinline__ int face_bucket(long long f, int M, const int32_t* nrows, const int32_t* tmpl) {
+  if (tmpl && tmpl[f] >= 0) return kMaxBins + 1;
+  const int N = nrows[f];
+  return (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
+}
+
 __global__ __launch_bounds__(256) void k_bin_count(long long n_face, int M, const int32_t* __restrict__ nrows,
-                                                   int32_t* bins) {
+                                                   const int32_t* __restrict__ tmpl, int32_t* bins) {
   __shared__ int32_t h[kNBuckets];
   if (threadIdx.x < kNBuckets) h[threadIdx.x] = 0;
   __syncthreads();
   long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (f < n_face) {
-    const int N = nrows[f];
-    const int b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
-    atomicAdd(&h[b], 1);
-  }
+  if (f < n_face) atomicAdd(&h[face_bucket(f, M, nrows, tmpl)], 1);
   __syncthreads();
   if (threadIdx.x < kNBuckets && h[threadIdx.x]) atomicAdd(&bins[threadIdx.x], h[threadIdx.x]);
 }
@@ -607,7 +609,7 @@ __global__ void k_bin_starts(int32_t* bins) {
 
 // each block ranks its faces per bucket in LDS, then reserves one range per bucket
 __global__ __launch_bounds__(256) void k_bin_scatter(long long n_face, int M, const int32_t* __restrict__ nrows,
-                                                     int32_t* bins, int32_t* perm) {
+                                                     const int32_t* __restrict__ tmpl, int32_t* bins, int32_t* perm) {
   __shared__ int32_t h[kNBuckets];
   __shared__ int32_t base[kNBuckets];
   if (threadIdx.x < kNBuckets) h[threadIdx.x] = 0;
@@ -615,8 +617,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(long long n_face, int M, co
   long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   int b = -1, r = 0;
   if (f < n_face) {
-    const int N = nrows[f];
-    b = (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
+    b = face_bucket(f, M, nrows, tmpl);
     r = atomicAdd(&h[b], 1);
   }
   __syncthreads();
@@ -654,13 +655,129 @@ int rows_per_face(const Work& w, long long n_face, const int64_t* row_ptr, hipSt
   return CUTCELL_OK;
 }
 
-int bin_faces(const Work& w, long long n_face, int M, hipStream_t st) {
+int bin_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins, (long long)(2 * kNBuckets), 0);
   if (n_face <= 0) return CUTCELL_OK;
-  hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, w.bins);
+  hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, tmpl, w.bins);
   hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, st, w.bins);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, w.bins,
-                     w.perm);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, tmpl,
+                     w.bins, w.perm);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Template reuse.  A face between two cells whose every neighbour within the path radius
+// is a plain interior volume has the fixed row pattern of the fast path above; if all of
+// those cells and their faces also carry exactly the reference cell's moments, its system
+// (rows about x0 -- the offsets are exact small half-integers --, weights and F) is bit
+// for bit that of any other such face of the same direction, and so is its stencil.  One
+// face per (geometry, direction) is solved; the others copy its values.
+
+constexpr int32_t kNone = 0x7fffffff;
+
+__global__ void k_ref_cell(GridDims g, const uint8_t* __restrict__ ballreg, int32_t* ref) {
+  const int gi = blockIdx.y;
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  if (ballreg[(long long)gi * g.ncell + c]) atomicMin(&ref[gi], (int32_t)c);
+}
+
+__device__ __forceinline__ bool same_bits(const double* a, const double* b, int n) {
+  bool s = true;
+  for (int i = 0; i < n; ++i) s = s && (__double_as_longlong(a[i]) == __double_as_longlong(b[i]));
+  return s;
+}
+
+// plain interior volume (as for ball regularity) whose volume moments and the moments of
+// its 2D faces equal the reference cell's bit for bit
+__global__ void k_canon0(GridDims g, int M, int Mf, const GeomPtrs* __restrict__ geoms,
+                         const uint8_t* __restrict__ info, const int32_t* __restrict__ ref, uint8_t* __restrict__ out) {
+  const int gi = blockIdx.y;
+  const long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (c >= g.ncell) return;
+  const long long o = (long long)gi * g.ncell + c;
+  const unsigned full = (1u << (1 + 2 * g.D)) - 1u;
+  bool r = info[o] == full;
+  const int x[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+  for (int d = 0; d < g.D; ++d) r = r && x[d] >= 1 && x[d] <= g.n[d] - 2;
+  const int32_t rc = ref[gi];
+  r = r && rc != kNone;
+  if (r) {
+    const GeomPtrs gp = geoms[gi];
+    r = same_bits(gp.vol_mom + c * M, gp.vol_mom + (long long)rc * M, M);
+    const int xr[3] = {(int)(rc % g.n[0]), (int)((rc / g.n[0]) % g.n[1]), (int)(rc / ((long long)g.n[0] * g.n[1]))};
+    for (int d = 0; d < g.D && r; ++d)
+      for (int s = 0; s < 2 && r; ++s) {
+        int j[3] = {x[0], x[1], x[2]}, jr[3] = {xr[0], xr[1], xr[2]};
+        j[d] += s;
+        jr[d] += s;
+        const long long lf = lattice_index(g, d, j) - g.foff[d], lr = lattice_index(g, d, jr) - g.foff[d];
+        r = same_bits(gp.face_mom[d] + lf * Mf, gp.face_mom[d] + lr * Mf, Mf);
+      }
+  }
+  out[o] = r ? 1 : 0;
+}
+
+// a grid face between two cells that are canonical out to the path radius
+__device__ __forceinline__ bool template_face(const GridDims& g, const int32_t* fcode, const int32_t* fref,
+                                             const uint8_t* canon, long long F, int* gi_out, int* dn_out) {
+  const int32_t code = fcode[F];
+  const int gi = code >> 4, kind = (code >> 2) & 3, dn = code & 3;
+  *gi_out = gi;
+  *dn_out = dn;
+  if (kind != 0) return false;
+  int j[3];
+  lattice_coords(g, dn, fref[F], j);
+  if (j[dn] < 1 || j[dn] > g.n[dn] - 1) return false;
+  const long long b = cell_index(g, j);
+  const long long st[3] = {1, g.n[0], (long long)g.n[0] * g.n[1]};
+  const uint8_t* cn = canon + (long long)gi * g.ncell;
+  return cn[b - st[dn]] && cn[b];
+}
+
+__global__ void k_tmpl_pick(GridDims g, long long n_face, const int32_t* __restrict__ fcode,
+                            const int32_t* __restrict__ fref, const uint8_t* __restrict__ canon, int32_t* tface) {
+  const long long F = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (F >= n_face) return;
+  int gi, dn;
+  if (template_face(g, fcode, fref, canon, F, &gi, &dn)) atomicMin(&tface[3 * gi + dn], (int32_t)F);
+}
+
+__global__ void k_tmpl_assign(GridDims g, long long n_face, const int32_t* __restrict__ fcode,
+                              const int32_t* __restrict__ fref, const uint8_t* __restrict__ canon,
+                              const int32_t* __restrict__ tface, int32_t* __restrict__ tmpl) {
+  const long long F = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (F >= n_face) return;
+  int gi, dn;
+  const bool q = template_face(g, fcode, fref, canon, F, &gi, &dn);
+  const int32_t t = q ? tface[3 * gi + dn] : kNone;
+  tmpl[F] = (q && t != (int32_t)F) ? t : -1;
+}
+
+int find_templates(const Work& w, const cutcell_opts& o, long long n_face, hipStream_t st) {
+  const GridDims& g = w.dims;
+  const int D = o.dim, Q = o.order;
+  const int M = binom(Q + D, D), Mf = binom(Q + D - 1, D - 1);
+  const int T = 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.ref_cell, (long long)w.G, kNone);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(3LL * w.G, 64)), dim3(64), 0, st, w.tface, 3LL * w.G, kNone);
+  hipLaunchKernelGGL(k_ref_cell, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, w.ballreg, w.ref_cell);
+  // R erosions must leave the result in w.canon (ping-pong with ballreg_tmp)
+  uint8_t* bufs[2] = {w.canon, w.ballreg_tmp};
+  int cur = (o.path_radius % 2 == 0) ? 0 : 1;
+  hipLaunchKernelGGL(k_canon0, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, M, Mf, w.geoms, w.cellinfo,
+                     w.ref_cell, bufs[cur]);
+  for (int r = 0; r < o.path_radius; ++r) {
+    hipLaunchKernelGGL(k_erode, dim3(blocks_for(g.ncell, T), w.G), dim3(T), 0, st, g, bufs[cur], bufs[1 - cur]);
+    cur = 1 - cur;
+  }
+  if (n_face > 0) {
+    hipLaunchKernelGGL(k_tmpl_pick, dim3(blocks_for(n_face, T)), dim3(T), 0, st, g, n_face, w.fcode, w.fref, w.canon,
+                       w.tface);
+    hipLaunchKernelGGL(k_tmpl_assign, dim3(blocks_for(n_face, T)), dim3(T), 0, st, g, n_face, w.fcode, w.fref,
+                       w.canon, w.tface, w.tmpl);
+  }
   CC_HIP(hipGetLastError());
   return CUTCELL_OK;
 }

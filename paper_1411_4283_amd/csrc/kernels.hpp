@@ -11,7 +11,7 @@ __host__ __device__ inline int32_t face_code(int g, int kind, int d) { return (g
 constexpr int kMaxBins = 8;     // row-count bins of 16 rows: N <= 16, 32, ..., 128
 constexpr int kBinRows = 16;
 constexpr int kMaxRows = kMaxBins * kBinRows;
-constexpr int kNBuckets = kMaxBins + 1;   // the last bucket holds faces with N < M
+constexpr int kNBuckets = kMaxBins + 2;   // then faces with N < M, then template copies
 constexpr int kBinWords = 2 * kNBuckets + 1;  // counts, cursors, max rows
 constexpr int kXcds = 8;        // MI355X: workgroups are dealt to 8 XCDs (own L2 each) in turn
 
@@ -34,6 +34,10 @@ struct Work {
   uint8_t* cellinfo;    // [G][ncell]  volume / open-face / EB bits for the neighbour search
   uint8_t* ballreg;     // [G][ncell]  1: every cell within path radius is a plain interior volume
   uint8_t* ballreg_tmp; // [G][ncell]  erosion ping-pong buffer
+  uint8_t* canon;       // [G][ncell]  1: every cell within path radius has the reference moments
+  int32_t* ref_cell;    // [G]         the reference (ball-regular) cell, or INT32_MAX
+  int32_t* tface;       // [G][3]      template face per direction, or INT32_MAX
+  int32_t* tmpl;        // [G*maxface] template of each face whose stencil is copied, else -1
   int64_t* counts;      // [G][4]      n_vol, n_eb, n_box, n_gface
   int64_t* offs;        // [3][G+1]    phi_off, vol_off, face_off
   int32_t* fcode;       // [G*maxface] per global flux face
@@ -87,7 +91,10 @@ int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const
 int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, int32_t* vol_face,
                   double* vol_scale, hipStream_t st);
 // binning by row count and the stencil solves (Sec. 2.2.1)
-int bin_faces(const Work& w, long long n_face, int M, hipStream_t st);
+// `tmpl` (or null): faces with tmpl >= 0 go to the template-copy bucket
+int bin_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hipStream_t st);
+// faces whose systems are bitwise those of one solved face per (geometry, direction)
+int find_templates(const Work& w, const cutcell_opts& o, long long n_face, hipStream_t st);
 int max_rows(const Work& w, long long n_face, hipStream_t st);
 int solve_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count /* host */, long long n_face,
                    const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st);

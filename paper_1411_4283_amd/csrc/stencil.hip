@@ -757,6 +757,26 @@ __global__ void k_insufficient(const int32_t* __restrict__ perm, long long n, co
   atomicAdd(flagged, 1);
 }
 
+// Faces whose system is bitwise that of their template face: the template's values (the
+// same rows in the same order) and status.  One wave per face.
+__global__ __launch_bounds__(64) void k_copy_template(const int32_t* __restrict__ perm, long long n,
+                                                      const int32_t* __restrict__ tmpl,
+                                                      const int64_t* __restrict__ row_ptr, double* val, int8_t* status,
+                                                      int32_t* flagged) {
+  const long long t = blockIdx.x;
+  if (t >= n) return;
+  const int32_t F = perm[t];
+  const int32_t T = tmpl[F];
+  const int64_t a = row_ptr[F], b = row_ptr[T];
+  const int N = (int)(row_ptr[F + 1] - a);
+  for (int i = threadIdx.x; i < N; i += 64) val[a + i] = val[b + i];
+  if (threadIdx.x == 0) {
+    const int8_t s = status[T];
+    status[F] = s;
+    if (s != CUTCELL_STATUS_OK) atomicAdd(flagged, 1);
+  }
+}
+
 static StencilArgs stencil_args(const Work& w, double hscale, const int32_t* perm, long long nbin,
                                 const int64_t* row_ptr, const int32_t* col) {
   StencilArgs A;
@@ -860,6 +880,10 @@ static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count,
     }
   }
   const long long ninsuf = (only_bin < 0) ? bin_count[kMaxBins] : 0;
+  const long long ncopy = (only_bin < 0 && !bw) ? bin_count[kMaxBins + 1] : 0;
+  if (ncopy > 0)   // after the bins: the templates are solved by then (same stream)
+    hipLaunchKernelGGL(k_copy_template, dim3((unsigned)ncopy), dim3(64), 0, st, w.perm + start + bin_count[kMaxBins],
+                       ncopy, w.tmpl, row_ptr, val, status, w.flagged);
   if (ninsuf > 0 && bw)
     hipLaunchKernelGGL(k_insufficient_backward, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st,
                        w.perm + start, ninsuf, row_ptr, (int)M, *bw);

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 5
+    assert lib.cutcell_abi_version() == 6
 
 
 def _opts(**kw):
