@@ -35,7 +35,7 @@ def log(msg):
 
 KERNEL_SOURCES = ("paper_1411_4283_amd/csrc/stencil.hip", "paper_1411_4283_amd/csrc/rows.hpp",
                   "paper_1411_4283_amd/csrc/common.hpp", "paper_1411_4283_amd/csrc/kernels.hpp",
-                  "paper_1411_4283_amd/csrc/apply.hip")
+                  "paper_1411_4283_amd/csrc/apply.hip", "paper_1411_4283_amd/csrc/gather.hpp")
 TRAFFIC_FILE = "profiles/traffic_3d_order4_sphere64.md"
 
 
@@ -293,7 +293,45 @@ def reuse_timings(torch, cc, dg, R, tuning, st_full, steps, n_face, full_ms):
             "bitwise_equal_to_full_build": bool(same)}
 
 
-def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200):
+def laplacian_timings(torch, cc, st, phi, face_apply_ms, reps=20):
+    """The operator as one matrix over volumes: its build (merge of each volume's face
+    rows) and its apply (one gather per volume), HIP events on the launch stream, median
+    of `reps`; algorithmic bytes as for the face apply (entries 12 B, row offsets, Phi and
+    the output once)."""
+    import numpy as np
+
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(n):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    holder = {}
+    build_ms = timed(lambda: holder.__setitem__("lap", cc.build_laplacian(st)), 5)
+    lap = holder["lap"]
+    lphi = torch.empty(max(st.sizes.n_vol, 1), dtype=torch.float64, device=phi.device)
+    ms = timed(lambda: cc.apply_laplacian(lap, phi, lphi), reps)
+    s = st.sizes
+    nbytes = 12 * lap.nnz + 8 * (s.n_vol + 1) + 8 * s.n_phi + 8 * s.n_vol
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"nnz": int(lap.nnz), "face_nnz": int(s.nnz), "build_ms": build_ms, "apply_ms": ms,
+           "bytes_per_launch": nbytes, "apply_gbps": gbs,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": gbs / PEAK_HBM_GBS, "kernel": "k_flux over volume rows"},
+           "speedup_vs_face_apply": face_apply_ms / ms}
+    return out, lap
+
+
+def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200, lap=None):
     """The discrete Poisson problem on the workload's geometry (Dirichlet data and source
     from the paper's 3D exact solution, Sec. 3.6) solved by the GPU GMRES (cutcell_solve);
     wall-clock time of the call, iterations, and the solution error against the exact
@@ -316,10 +354,10 @@ def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200):
     dev = st.val.device
     phi_t = torch.from_numpy(phi).to(dev)
     rhs_t = torch.from_numpy(rhs).to(dev)
-    cc.solve(st, phi_t, rhs_t, rtol=rtol, restart=restart, max_iters=5)   # warm-up
+    cc.solve(st, phi_t, rhs_t, rtol=rtol, restart=restart, max_iters=5, lap=lap)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = cc.solve(st, phi_t, rhs_t, rtol=rtol, restart=restart, max_iters=20000)
+    res = cc.solve(st, phi_t, rhs_t, rtol=rtol, restart=restart, max_iters=20000, lap=lap)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     e = res.x.cpu().numpy() - phi[: len(vols)]
@@ -328,7 +366,7 @@ def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200):
             "converged": res.converged, "rtol": rtol, "restart": restart,
             "apply_share": res.iters * apply_ms / ms, "n_vol": int(len(vols)),
             "error_Linf": float(np.abs(e).max()), "error_L1": float(np.sum(np.abs(e) * V) / V.sum()),
-            "preconditioner": "Jacobi (right)"}
+            "preconditioner": "Jacobi (right)", "matvec": "volume matrix" if lap is not None else "face fluxes"}
 
 
 def _oracle_chunk(faces):
@@ -398,6 +436,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the adjoints")
     ap.add_argument("--no-reuse", action="store_true", help="skip timing the template-reuse build")
     ap.add_argument("--no-solve", action="store_true", help="skip timing the GPU Poisson solve")
+    ap.add_argument("--no-laplacian", action="store_true", help="skip the volume-matrix build and apply")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 256 MiB device copy (reference kernel for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -544,9 +583,16 @@ def main():
     if not args.no_reuse:
         log("template reuse")
         out["template_reuse"] = reuse_timings(torch, cc, dg, w["R"], b.tuning, st, args.steps, s.n_face, ms_per_step)
+    lap = None
+    if not args.no_laplacian:
+        log("volume matrix")
+        out["laplacian"], lap = laplacian_timings(torch, cc, st, phi, apply_mean)
     if not args.no_solve:
         log("Poisson solve")
         out["poisson_solve"] = solve_timings(torch, cc, g, st, apply_mean)
+        if lap is not None:
+            out["poisson_solve_laplacian"] = solve_timings(torch, cc, g, st, out["laplacian"]["apply_ms"], lap=lap)
+    del lap
     del st, b, dg
     torch.cuda.empty_cache()
     if not args.no_batched and args.workload == "c3":

@@ -84,7 +84,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 6
+#define CUTCELL_ABI_VERSION 7
 
 enum {
   CUTCELL_OK = 0,
@@ -274,6 +274,36 @@ int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const c
                               const cutcell_geom_grad* grads, double* weight_bar, void* workspace,
                               size_t workspace_bytes, cutcell_stream_t stream);
 
+/* The operator as one sparse matrix over volumes (Sec. 2.2, eq. 'laplacian over V'):
+ *   lphi[v] = sum_{k in row v} val[k] phi[col[k]]  =  L_v of cutcell_apply,
+ * row v the sigma-signed, vol_scale-weighted merge of the stencil rows of v's faces
+ * (columns ascending and distinct; explicit zeros kept).  Device arrays owned by the
+ * caller: row_ptr [n_vol + 1], col and val [nnz] from cutcell_laplacian_count. */
+typedef struct {
+  int64_t* row_ptr;
+  int32_t* col;
+  double* val;
+} cutcell_laplacian;
+
+/* Bytes of workspace cutcell_laplacian_count needs. */
+size_t cutcell_laplacian_workspace_bytes(const cutcell_sizes* sizes);
+
+/* Row lengths and offsets of the volume matrix of the stencils `st`: writes row_ptr
+ * [n_vol + 1] (device) and the number of entries to *nnz (host).  Synchronises `stream`. */
+int cutcell_laplacian_count(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st, int64_t* row_ptr,
+                            int64_t* nnz, void* workspace, size_t workspace_bytes, cutcell_stream_t stream);
+
+/* Fills col and val of `lap` (row_ptr from cutcell_laplacian_count on the same stencils).
+ * Deterministic: equal columns of different faces are summed in face-slot order (low,
+ * high per direction, then the EB face).  Asynchronous on `stream`. */
+int cutcell_laplacian_fill(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
+                           const cutcell_laplacian* lap, cutcell_stream_t stream);
+
+/* lphi [n_vol] = lap phi (phi [n_phi]).  Agrees with cutcell_apply up to the order of
+ * the additions.  Asynchronous on `stream`. */
+int cutcell_apply_laplacian(const cutcell_sizes* sizes, int32_t dim, const cutcell_laplacian* lap, const double* phi,
+                            double* lphi, cutcell_stream_t stream);
+
 /* Bytes of workspace cutcell_solve needs for `restart` Krylov vectors (0 if restart is
  * outside [1, 1024]).  About (restart + 8) n_vol + 2 n_phi + n_face doubles. */
 size_t cutcell_solve_workspace_bytes(const cutcell_sizes* sizes, int32_t restart);
@@ -294,13 +324,16 @@ size_t cutcell_solve_workspace_bytes(const cutcell_sizes* sizes, int32_t restart
  *   rtol             stop when ||rhs - L([x | bc])||_2 <= rtol ||rhs - L([0 | bc])||_2,
  *                    tested on the true residual
  *   iters, relres    (host, may be NULL) iterations taken and the final relative residual
+ *   lap              (may be NULL) the volume matrix of the same stencils: the products
+ *                    then take one gather per volume (cutcell_apply_laplacian) instead of
+ *                    the face fluxes and their divergence
  * Returns CUTCELL_OK, CUTCELL_W_NOT_CONVERGED, or an error.  Inner products are summed in
  * a fixed order (512 partials per product), so the result does not vary between runs.
  * Synchronises `stream` (every Arnoldi step reads its inner products back). */
-int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st, const double* phi_bc,
-                  const double* rhs, double* x, int32_t restart, int32_t max_iters, double rtol,
-                  void* workspace, size_t workspace_bytes, int32_t* iters, double* relres,
-                  cutcell_stream_t stream);
+int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
+                  const cutcell_laplacian* lap, const double* phi_bc, const double* rhs, double* x,
+                  int32_t restart, int32_t max_iters, double rtol, void* workspace, size_t workspace_bytes,
+                  int32_t* iters, double* relres, cutcell_stream_t stream);
 
 /* Observability: when enabled (per calling thread), cutcell_build_stencils records HIP
  * events on its stream between its phases, and cutcell_last_profile copies the last

@@ -10,4 +10,4 @@ from .api import Builder, DeviceGeometry, Stencils, apply, build_stencils, make_
 from ._lib import CutcellError, LIB_PATH, load  # noqa: F401
 from .api import Transpose, apply_adjoint, build_transpose  # noqa: F401,E402
 from .autograd import CutCellOperator, OperatorApply, StencilBuild  # noqa: F401,E402
-from .api import SolveResult, solve  # noqa: F401,E402
+from .api import Laplacian, SolveResult, apply_laplacian, build_laplacian, solve  # noqa: F401,E402

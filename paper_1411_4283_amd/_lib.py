@@ -81,6 +81,14 @@ class TransposeArrays(ctypes.Structure):
     ]
 
 
+class LaplacianArrays(ctypes.Structure):
+    _fields_ = [
+        ("row_ptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("val", ctypes.c_void_p),
+    ]
+
+
 class GeomGrad(ctypes.Structure):
     _fields_ = [
         ("vol_mom", P),
@@ -128,9 +136,17 @@ SIGNATURES = {
                                                  ctypes.POINTER(TransposeArrays), P, P, ctypes.POINTER(GeomGrad), P, P,
                                                  ctypes.c_size_t, P]),
     "cutcell_solve_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes), ctypes.c_int32]),
-    "cutcell_solve": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P, P, P,
-                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t,
-                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), P]),
+    "cutcell_solve": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
+                                     ctypes.POINTER(LaplacianArrays), P, P, P, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_double, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double), P]),
+    "cutcell_laplacian_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
+    "cutcell_laplacian_count": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P,
+                                               ctypes.POINTER(ctypes.c_int64), P, ctypes.c_size_t, P]),
+    "cutcell_laplacian_fill": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
+                                              ctypes.POINTER(LaplacianArrays), P]),
+    "cutcell_apply_laplacian": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(LaplacianArrays),
+                                               P, P, P]),
     "cutcell_set_profiling": (None, [ctypes.c_int]),
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "cutcell_last_reused_faces": (ctypes.c_int64, []),

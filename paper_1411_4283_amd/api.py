@@ -13,8 +13,8 @@ from math import comb
 import torch
 
 from . import _lib
-from ._lib import (OK, W_NOT_CONVERGED, Geom, GeomGrad, Opts, Sizes, StencilArrays, TransposeArrays, Tuning, check,
-                   load)
+from ._lib import (OK, W_NOT_CONVERGED, Geom, GeomGrad, LaplacianArrays, Opts, Sizes, StencilArrays,
+                   TransposeArrays, Tuning, check, load)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -329,6 +329,58 @@ def apply(st: Stencils, phi: torch.Tensor, lphi: torch.Tensor | None = None, flu
 
 
 @dataclass
+class Laplacian:
+    """The operator as one sparse matrix over volumes (cutcell_laplacian_*)."""
+
+    dim: int
+    sizes: Sizes
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    nnz: int
+
+    def struct(self) -> LaplacianArrays:
+        s = LaplacianArrays()
+        s.row_ptr, s.col, s.val = _ptr(self.row_ptr), _ptr(self.col), _ptr(self.val)
+        return s
+
+
+def build_laplacian(st: Stencils, stream=None) -> Laplacian:
+    """Merge the stencil rows of every volume's faces into its row of L (count, then fill)."""
+    s = st.sizes
+    dev = st.val.device
+    lib = load()
+    nbytes = lib.cutcell_laplacian_workspace_bytes(ctypes.byref(s))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    row_ptr = torch.empty(s.n_vol + 1, dtype=torch.int64, device=dev)
+    nnz = ctypes.c_int64(0)
+    arr = st.struct()
+    rc = lib.cutcell_laplacian_count(ctypes.byref(s), st.dim, ctypes.byref(arr), _ptr(row_ptr), ctypes.byref(nnz),
+                                     _ptr(ws), nbytes, _stream(stream))
+    check(rc, "cutcell_laplacian_count", allow_flagged=False)
+    n = int(nnz.value)
+    lap = Laplacian(st.dim, s, row_ptr, torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+                    torch.empty(max(n, 1), dtype=torch.float64, device=dev), n)
+    la = lap.struct()
+    rc = lib.cutcell_laplacian_fill(ctypes.byref(s), st.dim, ctypes.byref(arr), ctypes.byref(la), _stream(stream))
+    check(rc, "cutcell_laplacian_fill", allow_flagged=False)
+    return lap
+
+
+def apply_laplacian(lap: Laplacian, phi: torch.Tensor, lphi: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """L(Phi) through the volume matrix (one gather per volume)."""
+    s = lap.sizes
+    _check_f64(phi, s.n_phi, "phi")
+    if lphi is None:
+        lphi = torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=phi.device)
+    la = lap.struct()
+    rc = load().cutcell_apply_laplacian(ctypes.byref(s), lap.dim, ctypes.byref(la), _ptr(phi), _ptr(lphi),
+                                        _stream(stream))
+    check(rc, "cutcell_apply_laplacian", allow_flagged=False)
+    return lphi[: s.n_vol]
+
+
+@dataclass
 class SolveResult:
     x: torch.Tensor        # volume values of the solution [n_vol]
     iters: int             # Arnoldi steps taken
@@ -337,10 +389,12 @@ class SolveResult:
 
 
 def solve(st: Stencils, phi_bc: torch.Tensor, rhs: torch.Tensor, x0: torch.Tensor | None = None,
-          restart: int = 200, max_iters: int = 5000, rtol: float = 1e-10, stream=None) -> SolveResult:
+          restart: int = 200, max_iters: int = 5000, rtol: float = 1e-10, stream=None,
+          lap: "Laplacian | None" = None) -> SolveResult:
     """Solve L([x | bc]) = rhs for the volume values x (cutcell_solve: restarted GMRES with
-    right Jacobi preconditioning on the GPU).  `phi_bc` holds the Dirichlet values in its
-    EB and box entries; its volume entries are ignored."""
+    right Jacobi preconditioning on the GPU).  `phi_bc` holds the boundary data in its EB
+    and box entries; its volume entries are ignored.  With `lap` (build_laplacian of the
+    same stencils) the products use the volume matrix."""
     s = st.sizes
     _check_f64(phi_bc, s.n_phi, "phi_bc")
     _check_f64(rhs, s.n_vol, "rhs")
@@ -354,8 +408,10 @@ def solve(st: Stencils, phi_bc: torch.Tensor, rhs: torch.Tensor, x0: torch.Tenso
     it = ctypes.c_int32(0)
     rr = ctypes.c_double(0.0)
     arr = st.struct()
-    rc = load().cutcell_solve(ctypes.byref(s), st.dim, ctypes.byref(arr), _ptr(phi_bc), _ptr(rhs), _ptr(x), restart,
-                              max_iters, rtol, _ptr(ws), nbytes, ctypes.byref(it), ctypes.byref(rr), _stream(stream))
+    la = ctypes.byref(lap.struct()) if lap is not None else None
+    rc = load().cutcell_solve(ctypes.byref(s), st.dim, ctypes.byref(arr), la, _ptr(phi_bc), _ptr(rhs), _ptr(x),
+                              restart, max_iters, rtol, _ptr(ws), nbytes, ctypes.byref(it), ctypes.byref(rr),
+                              _stream(stream))
     if rc not in (OK, W_NOT_CONVERGED):
         check(rc, "cutcell_solve", allow_flagged=False)
     return SolveResult(x[: s.n_vol], int(it.value), float(rr.value), rc == OK)

@@ -410,9 +410,41 @@ size_t cutcell_solve_workspace_bytes(const cutcell_sizes* sizes, int32_t restart
   return solve_workspace_bytes(sizes->n_vol, sizes->n_phi, sizes->n_face, restart);
 }
 
-int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const double* phi_bc,
-                  const double* rhs, double* x, int32_t restart, int32_t max_iters, double rtol, void* workspace,
-                  size_t workspace_bytes, int32_t* iters, double* relres, cutcell_stream_t stream) {
+size_t cutcell_laplacian_workspace_bytes(const cutcell_sizes* sizes) {
+  if (!sizes || sizes->n_vol < 0) return 0;
+  return laplacian_temp_bytes(sizes->n_vol);
+}
+
+int cutcell_laplacian_count(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, int64_t* row_ptr,
+                            int64_t* nnz, void* workspace, size_t workspace_bytes, cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !row_ptr || !nnz || !workspace)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (sizes->n_vol < 0 || sizes->n_vol >= (1LL << 31)) return fail(CUTCELL_E_INVALID_ARG, "bad sizes");
+  return laplacian_count(dim, sizes->n_vol, st_->row_ptr, st_->col, st_->val, st_->vol_face, st_->vol_scale, row_ptr,
+                         nnz, (char*)workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+int cutcell_laplacian_fill(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_,
+                           const cutcell_laplacian* lap, cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !lap || !lap->row_ptr || !lap->col || !lap->val)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  return laplacian_fill(dim, sizes->n_vol, st_->row_ptr, st_->col, st_->val, st_->vol_face, st_->vol_scale,
+                        lap->row_ptr, lap->col, lap->val, (hipStream_t)stream);
+}
+
+int cutcell_apply_laplacian(const cutcell_sizes* sizes, int32_t dim, const cutcell_laplacian* lap, const double* phi,
+                            double* lphi, cutcell_stream_t stream) {
+  if (!sizes || !lap || !lap->row_ptr || !lap->col || !lap->val || !phi || !lphi)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  return apply_laplacian(dim, sizes->n_vol, lap->row_ptr, lap->col, lap->val, phi, lphi, (hipStream_t)stream);
+}
+
+int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const cutcell_laplacian* lap,
+                  const double* phi_bc, const double* rhs, double* x, int32_t restart, int32_t max_iters, double rtol,
+                  void* workspace, size_t workspace_bytes, int32_t* iters, double* relres, cutcell_stream_t stream) {
   if (!sizes || !stencils_complete(st_) || !st_->phi_off || !st_->vol_off || !phi_bc || !rhs || !x || !workspace)
     return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
   if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
@@ -426,6 +458,12 @@ int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
   if (sizes->n_vol == 0) return CUTCELL_OK;
   SolveOp op{dim, sizes->n_vol, sizes->n_phi, sizes->n_face, st_->row_ptr, st_->col, st_->val, st_->vol_face,
              st_->vol_scale, (hipStream_t)stream};
+  if (lap) {
+    if (!lap->row_ptr || !lap->col || !lap->val) return fail(CUTCELL_E_INVALID_ARG, "lap arrays are NULL");
+    op.lap_ptr = lap->row_ptr;
+    op.lap_col = lap->col;
+    op.lap_val = lap->val;
+  }
   int it = 0;
   const int rc = solve_poisson(op, sizes->n_geom, st_->phi_off, st_->vol_off, phi_bc, rhs, x, restart, max_iters,
                                rtol, (char*)workspace, workspace_bytes, &it, relres);

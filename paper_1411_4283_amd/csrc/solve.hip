@@ -84,21 +84,42 @@ __global__ void k_jacobi(long long n_vol, const int32_t* __restrict__ vol_face, 
   dinv[v] = (a != 0.0 && isfinite(a)) ? 1.0 / a : 1.0;
 }
 
-// partial[i][b] = sum over block b's slice of V_i . w for i < k (V row-major [k][n])
-__global__ __launch_bounds__(kDotBlock) void k_mdot(long long n, int k, const double* __restrict__ V,
+// partial[i][b] = block b's share of V_i . w for i < k, and of w . w as entry k when
+// `self` (V row-major [k][n]).  Eight products per pass over w; each is summed per thread
+// in a fixed order, across the wave by butterfly shuffles, then over the block's waves.
+constexpr int kChunk = 8;
+__global__ __launch_bounds__(kDotBlock) void k_mdot(long long n, int k, int self, const double* __restrict__ V,
                                                      const double* __restrict__ w, double* __restrict__ partial) {
-  __shared__ double red[kDotBlock];
-  for (int i = 0; i < k; ++i) {
-    double s = 0.0;
-    for (long long t = blockIdx.x * (long long)kDotBlock + threadIdx.x; t < n; t += (long long)kDotBlocks * kDotBlock)
-      s = fma(V[i * n + t], w[t], s);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = kDotBlock / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
+  __shared__ double red[kDotBlock / 64][kChunk];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kk = k + (self ? 1 : 0);
+  for (int i0 = 0; i0 < kk; i0 += kChunk) {
+    double acc[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) acc[u] = 0.0;
+    for (long long t = blockIdx.x * (long long)kDotBlock + threadIdx.x; t < n; t += (long long)kDotBlocks * kDotBlock) {
+      const double wt = w[t];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const int i = i0 + u;
+        if (i < k) acc[u] = fma(V[(long long)i * n + t], wt, acc[u]);
+        else if (i == k && self) acc[u] = fma(wt, wt, acc[u]);
+      }
     }
-    if (threadIdx.x == 0) partial[i * kDotBlocks + blockIdx.x] = red[0];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) red[wv][u] = acc[u];
+    __syncthreads();
+    if ((int)threadIdx.x < kChunk) {
+      double sum = 0.0;
+      for (int q = 0; q < kDotBlock / 64; ++q) sum += red[q][threadIdx.x];
+      const int i = i0 + threadIdx.x;
+      if (i < kk) partial[(long long)i * kDotBlocks + blockIdx.x] = sum;
+    }
     __syncthreads();
   }
 }
@@ -108,7 +129,7 @@ __global__ __launch_bounds__(kDotBlock) void k_mdot_final(const double* __restri
   __shared__ double red[kDotBlock];
   const int i = blockIdx.x;
   double s = 0.0;
-  for (int b = threadIdx.x; b < kDotBlocks; b += kDotBlock) s += partial[i * kDotBlocks + b];
+  for (int b = threadIdx.x; b < kDotBlocks; b += kDotBlock) s += partial[(long long)i * kDotBlocks + b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = kDotBlock / 2; off > 0; off >>= 1) {
@@ -116,6 +137,27 @@ __global__ __launch_bounds__(kDotBlock) void k_mdot_final(const double* __restri
     __syncthreads();
   }
   if (threadIdx.x == 0) out[i] = red[0];
+}
+
+// After the second Gram-Schmidt pass: d holds its coefficients c[0..k) and, in d[k], the
+// squared norm of the vector it started from, so the new norm is sqrt(d[k] - |c|^2) (c is
+// at rounding level after the first pass).  hn[0] = norm, hn[1] = 1/norm (0 if the norm
+// vanishes: a lucky breakdown).
+__global__ void k_norm_after(const double* __restrict__ d, int k, double* __restrict__ hn) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double c2 = 0.0;
+  for (int i = 0; i < k; ++i) c2 = fma(d[i], d[i], c2);
+  const double q = d[k] - c2;
+  const double r = q > 0.0 ? sqrt(q) : 0.0;
+  hn[0] = r;
+  hn[1] = r > 0.0 ? 1.0 / r : 0.0;
+}
+
+// out = s[1] * w (s on the device)
+__global__ void k_scale_dev(long long n, const double* __restrict__ w, const double* __restrict__ sc,
+                            double* __restrict__ out) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t < n) out[t] = w[t] * sc[1];
 }
 
 // w -= sum_{i<k} c[i] V_i
@@ -128,12 +170,14 @@ __global__ void k_maxpy(long long n, int k, const double* __restrict__ c, const 
   w[t] = s;
 }
 
+static inline size_t coef_words(int m) { return (size_t)(m + 1) + (m + 2) + 2; }   // pass 1 | pass 2 | norm
+
 size_t solve_workspace_bytes(long long n_vol, long long n_phi, long long n_face, int m) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t nv = std::max<long long>(n_vol, 1);
   return al(sizeof(double) * n_phi) * 2 + al(sizeof(double) * std::max<long long>(n_face, 1)) +
          al(sizeof(double) * nv) * 5 + al(sizeof(int32_t) * nv) + al(sizeof(double) * nv * (m + 1)) +
-         al(sizeof(double) * kDotBlocks * (m + 1)) + al(sizeof(double) * (m + 1)) * 2;
+         al(sizeof(double) * kDotBlocks * (m + 2)) + al(sizeof(double) * coef_words(m)) + al(sizeof(double) * (m + 1));
 }
 
 int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_t* vol_off, const double* phi_bc,
@@ -156,14 +200,19 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
   double* tmp = (double*)take(sizeof(double) * nv);
   int32_t* vphi = (int32_t*)take(sizeof(int32_t) * nv);
   double* V = (double*)take(sizeof(double) * nv * (m + 1));
-  double* partial = (double*)take(sizeof(double) * kDotBlocks * (m + 1));
-  double* dots = (double*)take(sizeof(double) * (m + 1));
+  double* partial = (double*)take(sizeof(double) * kDotBlocks * (m + 2));
+  double* cbuf = (double*)take(sizeof(double) * coef_words(m));   // pass-1 | pass-2 coefficients | norm
   double* coef = (double*)take(sizeof(double) * (m + 1));
+  double* c1 = cbuf;
+  double* c2 = cbuf + (m + 1);
+  double* hnb = cbuf + (m + 1) + (m + 2);
+  std::vector<double> hc(coef_words(m));
   hipStream_t st = op.st;
   const int T = 256;
   const unsigned gv = nb(n, T);
 
   auto apply = [&](const double* p, double* out) {
+    if (op.lap_ptr) return apply_laplacian(op.D, n, op.lap_ptr, op.lap_col, op.lap_val, p, out, st);
     return apply_operator(op.D, op.n_face, n, op.row_ptr, op.col, op.val, op.vol_face, op.vol_scale, p, out, flux,
                           nullptr, st);
   };
@@ -172,11 +221,15 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
     hipLaunchKernelGGL(k_scatter, dim3(gv), dim3(T), 0, st, n, vphi, v, phi0);
     return apply(phi0, out);
   };
-  auto mdot = [&](int k, const double* vecs, const double* y, std::vector<double>& host) {
-    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(kDotBlock), 0, st, n, k, vecs, y, partial);
-    hipLaunchKernelGGL(k_mdot_final, dim3(k), dim3(kDotBlock), 0, st, partial, dots);
-    host.resize(k);
-    CC_HIP(hipMemcpyAsync(host.data(), dots, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  // V^T y (k vectors) and, with self, y.y as entry k, into out on the device
+  auto mdot = [&](int k, int self, const double* y, double* out) {
+    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(kDotBlock), 0, st, n, k, self, V, y, partial);
+    hipLaunchKernelGGL(k_mdot_final, dim3(k + self), dim3(kDotBlock), 0, st, partial, out);
+  };
+  // ||y||^2 read back to the host
+  auto norm2 = [&](const double* y, double* out) {
+    mdot(0, 1, y, hnb);
+    CC_HIP(hipMemcpyAsync(out, hnb, sizeof(double), hipMemcpyDeviceToHost, st));
     CC_HIP(hipStreamSynchronize(st));
     return (int)CUTCELL_OK;
   };
@@ -196,10 +249,10 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
   else
     hipLaunchKernelGGL(k_jacobi<2>, dim3(gv), dim3(T), 0, st, n, op.vol_face, op.vol_scale, op.row_ptr, op.col,
                        op.val, vphi, dinv);
-  std::vector<double> hd;
-  rc = mdot(1, b, b, hd);
+  double nb2 = 0.0;
+  rc = norm2(b, &nb2);
   if (rc) return rc;
-  const double bnorm = std::sqrt(hd[0]);
+  const double bnorm = std::sqrt(nb2);
   if (!std::isfinite(bnorm)) return fail(CUTCELL_E_INVALID_ARG, "non-finite right-hand side or boundary data");
   if (bnorm == 0.0) {               // the solution is x = 0
     hipLaunchKernelGGL(k_fill_f64, dim3(gv), dim3(T), 0, st, x, n, 0.0);
@@ -216,9 +269,10 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
     rc = matvec(x, tmp);
     if (rc) return rc;
     hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0, b, -1.0, tmp, V);
-    rc = mdot(1, V, V, hd);
+    double r2 = 0.0;
+    rc = norm2(V, &r2);
     if (rc) return rc;
-    const double beta = std::sqrt(hd[0]);
+    const double beta = std::sqrt(r2);
     res = beta;
     if (!(beta > rtol * bnorm) || it >= max_iters) break;
     hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0 / beta, V, 0.0, V, V);
@@ -231,17 +285,19 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
       hipLaunchKernelGGL(k_mul, dim3(gv), dim3(T), 0, st, n, dinv, vj, z);     // z = D^-1 v_j
       rc = matvec(z, w);
       if (rc) return rc;
-      std::vector<double> h(j + 1, 0.0);
-      for (int pass = 0; pass < 2; ++pass) {            // CGS2
-        rc = mdot(j + 1, V, w, hd);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j + 1, dots, V, w);
-        for (int i = 0; i <= j; ++i) h[i] += hd[i];
-      }
-      rc = mdot(1, w, w, hd);
-      if (rc) return rc;
-      const double hn = std::sqrt(hd[0]);
-      hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, hn > 0.0 ? 1.0 / hn : 0.0, w, 0.0, w, vn);
+      // classical Gram-Schmidt twice; the coefficients stay on the device, the new
+      // vector's norm comes from the second pass, and the host reads all of them once
+      mdot(j + 1, 0, w, c1);
+      hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j + 1, c1, V, w);
+      mdot(j + 1, 1, w, c2);
+      hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j + 1, c2, V, w);
+      hipLaunchKernelGGL(k_norm_after, dim3(1), dim3(1), 0, st, c2, j + 1, hnb);
+      hipLaunchKernelGGL(k_scale_dev, dim3(gv), dim3(T), 0, st, n, w, hnb, vn);
+      CC_HIP(hipMemcpyAsync(hc.data(), cbuf, sizeof(double) * coef_words(m), hipMemcpyDeviceToHost, st));
+      CC_HIP(hipStreamSynchronize(st));
+      std::vector<double> h(j + 1);
+      for (int i = 0; i <= j; ++i) h[i] = hc[i] + hc[(m + 1) + i];
+      const double hn = hc[(m + 1) + (m + 2)];
       // Givens rotations on column j of H
       for (int i = 0; i < j; ++i) {
         const double t = cs[i] * h[i] + sn[i] * h[i + 1];

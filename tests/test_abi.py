@@ -29,7 +29,8 @@ def test_header_declares_the_entry_points():
     for n in ("cutcell_query", "cutcell_build_stencils", "cutcell_apply", "cutcell_workspace_bytes",
               "cutcell_last_error", "cutcell_abi_version", "cutcell_stencils_backward", "cutcell_apply_adjoint",
               "cutcell_build_transpose", "cutcell_transpose_workspace_bytes", "cutcell_backward_workspace_bytes",
-              "cutcell_solve", "cutcell_solve_workspace_bytes"):
+              "cutcell_solve", "cutcell_solve_workspace_bytes", "cutcell_laplacian_count", "cutcell_laplacian_fill",
+              "cutcell_apply_laplacian", "cutcell_laplacian_workspace_bytes", "cutcell_last_reused_faces"):
         assert n in names
 
 
@@ -40,7 +41,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 6
+    assert lib.cutcell_abi_version() == 7
 
 
 def _opts(**kw):
@@ -128,8 +129,8 @@ def test_solve_rejects_bad_arguments_on_the_host(lib, restart, max_iters, rtol, 
     sizes = _lib.Sizes(n_vol=10, n_eb=0, n_box=4, n_phi=14, n_face=20, nnz=100, max_rows=5, n_geom=1)
     arr = _fake_stencils()
     it = ctypes.c_int32(-1)
-    rc = lib.cutcell_solve(ctypes.byref(sizes), 2, ctypes.byref(arr), 8, 8, 8, restart, max_iters, rtol, 8, 1 << 20,
-                           ctypes.byref(it), None, None)
+    rc = lib.cutcell_solve(ctypes.byref(sizes), 2, ctypes.byref(arr), None, 8, 8, 8, restart, max_iters, rtol, 8,
+                           1 << 20, ctypes.byref(it), None, None)
     assert rc == code
     assert lib.cutcell_last_error()
 

@@ -1,0 +1,138 @@
+"""The operator as one sparse matrix over volumes (cutcell_laplacian_count / _fill,
+cutcell_apply_laplacian; Sec. 2.2, eq. 'laplacian over V').
+
+* Merge, exactly: each sampled row's columns are the sorted union of the columns of the
+  volume's face rows, and each value is vol_scale * (sum of sigma * s in face-slot order)
+  -- recomputed on the host in the same order, so the comparison is bit for bit.
+* Against the oracle's assembled matrix (Sec. 2.2) on the oracle's own stencils, per
+  entry within the stencil bar carried through the sum.
+* L(Phi) through the matrix equals the face-flux apply within the rounding bound of the
+  sums; the solve through the matrix reproduces the quartic averages like the face path.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import cutgeom as cg
+import oracle
+
+torch = pytest.importorskip("torch")
+import paper_1411_4283_amd as cc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _host_row(v, D, vf, vs, rp, col, val):
+    """(columns, values) of row v, merged on the host in face-slot order."""
+    S = 2 * D + 1
+    acc = {}
+    for k in range(S):
+        f = vf[v * S + k]
+        if f < 0:
+            continue
+        sg = -1.0 if (k < 2 * D and k % 2 == 0) else 1.0
+        for j in range(rp[f], rp[f + 1]):
+            c = int(col[j])
+            acc[c] = acc.get(c, 0.0) + sg * val[j]
+    cols = np.array(sorted(acc), dtype=np.int64)
+    return cols, np.array([vs[v] * acc[c] for c in cols])
+
+
+def _check_rows(st, lap, vols):
+    D = st.dim
+    s = st.sizes
+    vf = st.vol_face.cpu().numpy()
+    vs = st.vol_scale.cpu().numpy()
+    rp = st.row_ptr.cpu().numpy()
+    col = st.col.cpu().numpy()[: s.nnz]
+    val = st.val.cpu().numpy()[: s.nnz]
+    lp = lap.row_ptr.cpu().numpy()
+    lc = lap.col.cpu().numpy()[: lap.nnz]
+    lv = lap.val.cpu().numpy()[: lap.nnz]
+    assert lp[0] == 0 and lp[-1] == lap.nnz and np.all(np.diff(lp) >= 0)
+    for v in vols:
+        cols, vals = _host_row(int(v), D, vf, vs, rp, col, val)
+        a, b = lp[v], lp[v + 1]
+        assert np.array_equal(lc[a:b], cols), f"volume {v}: columns differ"
+        assert np.array_equal(lv[a:b], vals), f"volume {v}: values differ"
+
+
+CASES = {
+    "circle32_q4": (cg.ball_outside((0.5, 0.5), 0.25), 32, 4, 3, "dirichlet"),
+    "circle16_q2_neumann": (cg.ball_outside((0.5, 0.5), 0.25), 16, 2, 2, "neumann"),
+    "sphere10_q4": (cg.ball_outside((0.5, 0.5, 0.5), 0.3), 10, 4, 3, "dirichlet"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_laplacian_rows_and_oracle(name):
+    shape, n, Q, R, bc = CASES[name]
+    g = cg.make_geometry(shape, n, Q)
+    dg = cc.DeviceGeometry.from_host(g, DEV)
+    st = cc.Builder(dg, R, eb_bc=bc).build()
+    lap = cc.build_laplacian(st)
+    torch.cuda.synchronize()
+    _check_rows(st, lap, range(st.sizes.n_vol))
+    # against the oracle's matrix on its own stencils (dense rows)
+    en, rp, col, val, status = oracle.build(g, R, eb_bc=bc)
+    A = oracle.operator_matrix(g, en, rp, col, val).toarray()
+    lp = lap.row_ptr.cpu().numpy()
+    lc = lap.col.cpu().numpy()[: lap.nnz]
+    lv = lap.val.cpu().numpy()[: lap.nnz]
+    Ag = np.zeros_like(A)
+    for v in range(en.n_vol):
+        Ag[v, lc[lp[v]:lp[v + 1]]] = lv[lp[v]:lp[v + 1]]
+    # per entry: the stencil bar (1e-11 of each face's largest value, faces here have
+    # cond < 1e5) times the volume scale, summed over the volume's faces
+    S = 2 * g.D + 1
+    vf = st.vol_face.cpu().numpy()
+    vs = st.vol_scale.cpu().numpy()
+    fmax = np.array([np.abs(val[rp[f]:rp[f + 1]]).max() if rp[f + 1] > rp[f] else 0.0 for f in range(en.n_face)])
+    bound = np.array([vs[v] * sum(fmax[f] for f in vf[v * S:(v + 1) * S] if f >= 0) for v in range(en.n_vol)])
+    err = np.abs(Ag - A).max(axis=1)
+    assert np.all(err <= 1e-11 * bound), (err / bound).max()
+    _say(f"{name}: {en.n_vol} volumes, nnz {lap.nnz} (face nnz {len(col)}), worst entry err / bound "
+         f"{(err / np.maximum(bound, 1e-300)).max():.2e}")
+
+
+def test_laplacian_full_size_apply_and_solve():
+    g = cg.make_geometry(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 64, 4)
+    dg = cc.DeviceGeometry.from_host(g, DEV)
+    st = cc.Builder(dg, 3).build()
+    lap = cc.build_laplacian(st)
+    torch.cuda.synchronize()
+    s = st.sizes
+    _say(f"sphere64: nnz {lap.nnz} vs face nnz {s.nnz}")
+    rng = np.random.default_rng(4)
+    _check_rows(st, lap, rng.choice(s.n_vol, 400, replace=False))
+    lap2 = cc.build_laplacian(st)
+    assert torch.equal(lap.val, lap2.val) and torch.equal(lap.col, lap2.col)
+    phi = torch.from_numpy(rng.standard_normal(s.n_phi)).to(DEV)
+    L1, flux = cc.apply(st, phi)
+    L2 = cc.apply_laplacian(lap, phi)
+    # rounding bound of either sum: 1e-12 of sum |s Phi| / |V| per volume
+    absflux = cc.apply(st, phi.abs(), val=st.val.abs().contiguous())[1]
+    vf = st.vol_face.cpu().numpy().reshape(s.n_vol, 7)
+    af = absflux.cpu().numpy()
+    scale = st.vol_scale.cpu().numpy() * np.where(vf >= 0, af[np.maximum(vf, 0)], 0.0).sum(axis=1)
+    d = np.abs(L1.cpu().numpy() - L2.cpu().numpy())
+    assert np.all(d <= 1e-12 * scale), (d / scale).max()
+    # the solve through the matrix: quartic averages, as through the face path
+    from test_gpu_solve import _exact_phi_and_rhs, _t
+    en = oracle.enumerate_geometry(g)
+    ph, rhs = _exact_phi_and_rhs(g, en, cg.random_polynomial(3, 4, np.random.default_rng(12), scale=0.5))
+    r1 = cc.solve(st, _t(ph), _t(rhs), rtol=1e-13, restart=200, max_iters=20000)
+    r2 = cc.solve(st, _t(ph), _t(rhs), rtol=1e-13, restart=200, max_iters=20000, lap=lap)
+    assert r1.converged and r2.converged
+    e1 = np.abs(r1.x.cpu().numpy() - ph[: en.n_vol]).max() / np.abs(ph).max()
+    e2 = np.abs(r2.x.cpu().numpy() - ph[: en.n_vol]).max() / np.abs(ph).max()
+    _say(f"quartic solve: face path {r1.iters} it, err {e1:.2e}; matrix {r2.iters} it, err {e2:.2e}")
+    assert e2 <= 1e-8 and abs(r1.iters - r2.iters) <= 0.05 * r1.iters + 2
