@@ -331,6 +331,61 @@ def laplacian_timings(torch, cc, st, phi, face_apply_ms, reps=20):
     return out, lap
 
 
+def weight_study(torch, cc, powers=(0.0, 2.0, 3.0, 4.0, 5.0, 6.0, 8.0)):
+    """Sec. 2.4's weights W = (2d)^-p beyond half a cell, p swept on the paper's spectrum
+    case (64 x 64 grid outside the circle r = 0.25, fourth order, path radius 3, Dirichlet):
+    per p, the rightmost and leftmost eigenvalues from GPU Arnoldi (cutcell_ritz: 60 steps
+    on A, 20 shift-invert steps) and the L1 solution error of the GPU solve for the paper's
+    2D exact solution.  The paper uses p = 5."""
+    import numpy as np
+
+    import cutgeom as cg
+
+    g = cg.make_geometry(cg.ball_outside((0.5, 0.5), 0.25), 64, 4)
+    tp = 2 * math.pi
+    I = g.integrate(cg.trig_product((tp, tp), (-tp * math.sqrt(2) / 2, -tp * math.sqrt(3) / 2)))
+    hD, hD1 = g.h**2, g.h
+    kap = g.kappa
+    vol_avg = np.divide(I["vol_int"], kap * hD, out=np.zeros_like(kap), where=kap > 0)
+    face_avg = [np.divide(I["face_int"][d], g.alpha(d) * hD1, out=np.zeros(len(g.alpha(d))), where=g.alpha(d) > 0)
+                for d in range(2)]
+    phi = g.layout_phi(vol_avg, I["eb_int"] / (g.eb_mom[:, 0] * hD1), face_avg)
+    vols = np.nonzero(kap > 0)[0]
+    rhs = I["vol_lap"][vols] / (kap[vols] * hD)
+    V = kap[vols] * hD
+    dev = torch.device("cuda:0")
+    dg = cc.DeviceGeometry.from_host(g, dev)
+    phi_t = torch.from_numpy(phi).to(dev)
+    rhs_t = torch.from_numpy(rhs).to(dev)
+    rows = []
+    t0 = time.perf_counter()
+    for p in powers:
+        st = cc.Builder(dg, 3, weight_power=p).build()
+        r0, ok0 = cc.ritz(st, mode=0, steps=60)
+        r1, ok1 = cc.ritz(st, mode=1, steps=20, inner_rtol=1e-10)
+        res = cc.solve(st, phi_t, rhs_t, rtol=1e-13, restart=200, max_iters=4000)
+        e = res.x.cpu().numpy() - phi[: len(vols)]
+        rows.append({"p": p, "lambda_max": float(max(r0.real.max(), r1.real.max())),
+                     "lambda_min": float(r0.real.min()), "ritz_converged": bool(ok0 and ok1),
+                     "solve_converged": bool(res.converged), "solve_iterations": res.iters,
+                     "error_L1": float(np.sum(np.abs(e) * V) / V.sum()), "error_Linf": float(np.abs(e).max()),
+                     "flagged_faces": int(st.status.ne(0).sum())})
+        log(f"weight p={p}: {rows[-1]}")
+    return {"case": "64x64 outside circle r=0.25, order 4, path radius 3, Dirichlet", "rows": rows,
+            "seconds": time.perf_counter() - t0}
+
+
+def spectrum_at_scale(cc, st, lap):
+    """Rightmost and leftmost eigenvalues of the workload's operator (GPU Arnoldi through
+    the volume matrix)."""
+    t0 = time.perf_counter()
+    r1, ok1 = cc.ritz(st, mode=1, steps=20, lap=lap, inner_rtol=1e-10)
+    r0, ok0 = cc.ritz(st, mode=0, steps=60, lap=lap)
+    return {"lambda_max": float(max(r1.real.max(), r0.real.max())), "lambda_min": float(r0.real.min()),
+            "converged": bool(ok0 and ok1), "seconds": time.perf_counter() - t0,
+            "method": "Arnoldi: 20 shift-invert steps (GMRES inner solves, rtol 1e-10) and 60 steps on A"}
+
+
 def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200, lap=None):
     """The discrete Poisson problem on the workload's geometry (Dirichlet data and source
     from the paper's 3D exact solution, Sec. 3.6) solved by the GPU GMRES (cutcell_solve);
@@ -437,6 +492,7 @@ def main():
     ap.add_argument("--no-reuse", action="store_true", help="skip timing the template-reuse build")
     ap.add_argument("--no-solve", action="store_true", help="skip timing the GPU Poisson solve")
     ap.add_argument("--no-laplacian", action="store_true", help="skip the volume-matrix build and apply")
+    ap.add_argument("--no-weight-study", action="store_true", help="skip the weight-exponent study and spectra")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 256 MiB device copy (reference kernel for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -587,6 +643,11 @@ def main():
     if not args.no_laplacian:
         log("volume matrix")
         out["laplacian"], lap = laplacian_timings(torch, cc, st, phi, apply_mean)
+    if not args.no_weight_study:
+        log("weight study and spectra")
+        out["weight_study"] = weight_study(torch, cc)
+        if lap is not None:
+            out["spectrum_at_scale"] = spectrum_at_scale(cc, st, lap)
     if not args.no_solve:
         log("Poisson solve")
         out["poisson_solve"] = solve_timings(torch, cc, g, st, apply_mean)

@@ -41,7 +41,8 @@
  *    face those volumes touch; col[] lists their Phi indices in ascending order.
  *  Centring (Sec. 2.4).  x0 = face centre for grid faces; for an EB face the centroid
  *    of the cut volume.  Weights W_i = 1 if d_i < 1/2 else (2 d_i)^-5, d_i = |x_i - x0|/h,
- *    x_i the Cartesian centre of the row's cell (volume and EB rows) or face (box rows).
+ *    x_i the Cartesian centre of the row's cell (volume and EB rows) or face (box rows);
+ *    cutcell_opts.weight_custom / weight_power replace the exponent 5 for weight studies.
  *  Values.  val[] holds the physical stencil s = h^(D-2) W (A~^T W)^+ F~, so
  *    flux_f = sum_j val[j] Phi[col[j]] approximates int_f grad(phi).n dA, and
  *    L_v = (1/(kappa_v h^D)) sum_f sigma_vf flux_f with sigma = +1 when the face's
@@ -84,7 +85,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 7
+#define CUTCELL_ABI_VERSION 9
 
 enum {
   CUTCELL_OK = 0,
@@ -145,6 +146,10 @@ typedef struct {
                            for bit that of a build without reuse; only the work differs
                            (cutcell_last_reused_faces counts the copies).  0: solve every
                            face, as the paper does.                                     */
+  int32_t weight_custom;   /* 0: the paper's weights W = (2d)^-5 beyond half a cell
+                           (Sec. 2.4); 1: W = (2d)^-weight_power instead (weight studies;
+                           0 gives unweighted least squares)                            */
+  double weight_power;  /* used when weight_custom = 1; in [0, 16]                      */
 } cutcell_opts;
 
 enum { CUTCELL_BC_DIRICHLET = 0, CUTCELL_BC_NEUMANN = 1 };
@@ -334,6 +339,32 @@ int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
                   const cutcell_laplacian* lap, const double* phi_bc, const double* rhs, double* x,
                   int32_t restart, int32_t max_iters, double rtol, void* workspace, size_t workspace_bytes,
                   int32_t* iters, double* relres, cutcell_stream_t stream);
+
+/* Eigenvalues of an n x n upper Hessenberg matrix H (host arrays, row-major with leading
+ * dimension ld; entries below the subdiagonal are ignored) into re[n], im[n]: shifted QR
+ * iterations in complex arithmetic (Wilkinson shifts, deflation from the bottom).  Host
+ * only, no device work.  Returns CUTCELL_OK, or CUTCELL_E_BREAKDOWN if it fails to
+ * converge. */
+int cutcell_hessenberg_eigs(int32_t n, const double* H, int32_t ld, double* re, double* im);
+
+/* Bytes of workspace cutcell_ritz needs (mode 1 includes the inner solves'). */
+size_t cutcell_ritz_workspace_bytes(const cutcell_sizes* sizes, int32_t steps, int32_t mode, int32_t inner_restart);
+
+/* Ritz values of the volume operator A (L restricted to the volume values, every boundary
+ * entry of Phi zero; the spectra of Sec. 3.4 and 3.5) from `steps` Arnoldi steps on the
+ * GPU with a fixed pseudo-random start vector and classical Gram-Schmidt twice:
+ *   mode 0: on A -- the eigenvalues of largest magnitude converge first (lambda_min, and
+ *           any large positive eigenvalue of an unstable operator);
+ *   mode 1: on A^-1 (each step a cutcell_solve with inner_rtol, inner_restart,
+ *           inner_max_iters), values inverted -- the eigenvalues nearest 0 (lambda_max of
+ *           a stable operator).
+ * lap (may be NULL): the volume matrix for the products.  ritz_re/ritz_im [steps] (host)
+ * receive *n_ritz values (fewer than steps if an invariant subspace is found).  Returns
+ * CUTCELL_W_NOT_CONVERGED if an inner solve did not converge.  Synchronises `stream`. */
+int cutcell_ritz(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st, const cutcell_laplacian* lap,
+                 int32_t mode, int32_t steps, double inner_rtol, int32_t inner_restart, int32_t inner_max_iters,
+                 double* ritz_re, double* ritz_im, int32_t* n_ritz, void* workspace, size_t workspace_bytes,
+                 cutcell_stream_t stream);
 
 /* Observability: when enabled (per calling thread), cutcell_build_stencils records HIP
  * events on its stream between its phases, and cutcell_last_profile copies the last

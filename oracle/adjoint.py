@@ -100,7 +100,7 @@ def _row_moments(inp, en, idx):
     return torch.stack(rows)
 
 
-def _face_stencil_t(inp, en, f, R, wleaf=None):
+def _face_stencil_t(inp, en, f, R, wleaf=None, wpow=5.0):
     """Torch version of oracle.stencils.face_stencil (scaled s~, before h^(D-2))."""
     D, Q, h = en.D, en.Q, en.h
     idx = S.neighbours(en, f, R)
@@ -117,7 +117,7 @@ def _face_stencil_t(inp, en, f, R, wleaf=None):
     mom = _row_moments(inp, en, idx)
     A = _recentre_t(mom, delta, D, Q) / mom[:, :1]
     dist = torch.sqrt(torch.sum(delta * delta, dim=1))
-    W = torch.where(dist < 0.5, torch.ones_like(dist), (2.0 * torch.clamp(dist, min=0.5)) ** -5)
+    W = torch.where(dist < 0.5, torch.ones_like(dist), (2.0 * torch.clamp(dist, min=0.5)) ** -float(wpow))
     if wleaf is not None:
         W = wleaf
     # flux vector about x0
@@ -147,7 +147,7 @@ def _face_stencil_t(inp, en, f, R, wleaf=None):
     return W * y, W, idx
 
 
-def stencils_backward(geom, en, R, row_ptr, val_bar, faces=None, weights=True):
+def stencils_backward(geom, en, R, row_ptr, val_bar, faces=None, weights=True, wpow=5.0):
     """Gradient of sum_j val_bar[j] val[j] (val = h^(D-2) s~, the physical stencils) with
     respect to vol_mom, face_mom[d], eb_mom, eb_nmom, and (if `weights`) the weights (per
     nnz, holding the other inputs fixed).  Faces whose status is not OK contribute nothing."""
@@ -162,16 +162,16 @@ def stencils_backward(geom, en, R, row_ptr, val_bar, faces=None, weights=True):
         vb = torch.as_tensor(val_bar[a:b])
         if not np.any(val_bar[a:b]):
             continue
-        idx0, s0, status = S.face_stencil(geom, en, f, R)
+        idx0, s0, status = S.face_stencil(geom, en, f, R, wpow=wpow)
         if status != S.STATUS_OK:
             continue
-        s, W, idx = _face_stencil_t(inp, en, f, R)
+        s, W, idx = _face_stencil_t(inp, en, f, R, wpow=wpow)
         total = total + hs * torch.sum(vb * s)
         if not weights:
             continue
         # weights as free leaves: d/dW of the same objective
         wl = W.detach().clone().requires_grad_(True)
-        s_w, _, _ = _face_stencil_t(_detached(inp), en, f, R, wleaf=wl)
+        s_w, _, _ = _face_stencil_t(_detached(inp), en, f, R, wleaf=wl, wpow=wpow)
         gw, = torch.autograd.grad(hs * torch.sum(vb * s_w), wl)
         w_bar[a:b] = gw.numpy()
     if total.requires_grad:

@@ -300,10 +300,11 @@ def recentre(mom: np.ndarray, delta: np.ndarray, D: int, Q: int) -> np.ndarray:
     return (coef * powers * mom[..., qi]) @ P
 
 
-def row_weights(dist_over_h: np.ndarray) -> np.ndarray:
-    """W_ii of Sec. 2.4: 1 if |x_i - x0|/h < 1/2, else (2 |x_i - x0|/h)^-5."""
+def row_weights(dist_over_h: np.ndarray, wpow: float = 5.0) -> np.ndarray:
+    """W_ii of Sec. 2.4: 1 if |x_i - x0|/h < 1/2, else (2 |x_i - x0|/h)^-5; `wpow`
+    replaces the exponent 5 for weight studies (0: unweighted least squares)."""
     d = np.asarray(dist_over_h, dtype=np.float64)
-    return np.where(d < 0.5, 1.0, (2.0 * np.maximum(d, 0.5)) ** -5)
+    return np.where(d < 0.5, 1.0, (2.0 * np.maximum(d, 0.5)) ** -float(wpow))
 
 
 def flux_vector(geom, en: Enumeration, f: int, x0: np.ndarray) -> np.ndarray:
@@ -348,7 +349,8 @@ def eb_normal_flux(geom, en: Enumeration, e: int, x0: np.ndarray) -> np.ndarray:
     return F
 
 
-def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet"):
+def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet",
+                wpow: float = 5.0):
     """Rows A~ (N x M), weights W (N), flux vector F~ (M) and the Phi indices of face f.
 
     Rows follow eq. 'volume moment eq for cp' (volume averages: A_vp = m^p_v(x0)/m^0_v)
@@ -370,12 +372,13 @@ def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", 
                 A[i] = eb_normal_flux(geom, en, e, x0) / geom.eb_mom[e, 0]
     elif eb_bc != "dirichlet":
         raise ValueError(eb_bc)
-    W = row_weights(np.sqrt(np.sum(delta * delta, axis=1)))
+    W = row_weights(np.sqrt(np.sum(delta * delta, axis=1)), wpow)
     F = flux_vector(geom, en, f, x0)
     return A, W, F, idx
 
 
-def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet"):
+def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet",
+                 wpow: float = 5.0):
     """Stencil of face f: s = h^(D-2) W (A~^T W)^+ F~ (eq. 'stencil equation solution'),
     the solution of A~^T s~ = F~ of least ||W^-1 s~|| (Sec. 2.2.1).  The pseudo-inverse
     is applied as LAPACK's minimum-norm least-squares solve.  Under Neumann EB conditions
@@ -387,7 +390,7 @@ def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid",
         e = int(en.face_lin[f])
         return (np.array([en.n_vol + e], np.int64), np.array([geom.eb_mom[e, 0] * en.h ** (en.D - 1)]),
                 STATUS_OK)
-    A, W, F, idx = face_system(geom, en, f, R, eb_x0, eb_bc)
+    A, W, F, idx = face_system(geom, en, f, R, eb_x0, eb_bc, wpow)
     N, M = A.shape
     if not (np.all(np.isfinite(A)) and np.all(np.isfinite(F))):
         return idx, np.zeros(N), STATUS_NONFINITE
@@ -407,17 +410,17 @@ def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid",
     return idx, hs * W * y, STATUS_OK
 
 
-def face_condition(geom, en: Enumeration, f: int, R: int, eb_bc: str = "dirichlet") -> float:
+def face_condition(geom, en: Enumeration, f: int, R: int, eb_bc: str = "dirichlet", wpow: float = 5.0) -> float:
     """2-norm condition number of the column-equilibrated weighted matrix W A~."""
     if eb_bc == "neumann" and en.face_kind[f] == KIND_EB:
         return 1.0
-    A, W, F, idx = face_system(geom, en, f, R, eb_bc=eb_bc)
+    A, W, F, idx = face_system(geom, en, f, R, eb_bc=eb_bc, wpow=wpow)
     B = W[:, None] * A
     return float(np.linalg.cond(B / np.sqrt(np.sum(B * B, axis=0))))
 
 
 def build(geom, R: int, faces=None, en: Enumeration | None = None, eb_x0: str = "centroid",
-          eb_bc: str = "dirichlet"):
+          eb_bc: str = "dirichlet", wpow: float = 5.0):
     """Stencils of all flux faces (or of the listed ones) as CSR arrays
     (row_ptr int64, col int64, val float64, status int8); eb_bc selects Dirichlet or
     Neumann conditions on the embedded boundary (Sec. 2.2.1; box faces stay Dirichlet)."""
@@ -427,7 +430,7 @@ def build(geom, R: int, faces=None, en: Enumeration | None = None, eb_x0: str = 
     rp = [0]
     cols, vals, st = [], [], []
     for f in fl:
-        idx, s, status = face_stencil(geom, en, int(f), R, eb_x0, eb_bc)
+        idx, s, status = face_stencil(geom, en, int(f), R, eb_x0, eb_bc, wpow)
         cols.append(idx)
         vals.append(s)
         st.append(status)

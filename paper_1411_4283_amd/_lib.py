@@ -28,6 +28,8 @@ class Opts(ctypes.Structure):
         ("tuning", ctypes.POINTER(Tuning)),
         ("eb_bc", ctypes.c_int32),
         ("reuse_templates", ctypes.c_int32),
+        ("weight_custom", ctypes.c_int32),
+        ("weight_power", ctypes.c_double),
     ]
 
 
@@ -140,6 +142,13 @@ SIGNATURES = {
                                      ctypes.POINTER(LaplacianArrays), P, P, P, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_double, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_double), P]),
+    "cutcell_hessenberg_eigs": (ctypes.c_int, [ctypes.c_int32, P, ctypes.c_int32, P, P]),
+    "cutcell_ritz_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.c_int32]),
+    "cutcell_ritz": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
+                                    ctypes.POINTER(LaplacianArrays), ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32), P,
+                                    ctypes.c_size_t, P]),
     "cutcell_laplacian_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
     "cutcell_laplacian_count": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P,
                                                ctypes.POINTER(ctypes.c_int64), P, ctypes.c_size_t, P]),

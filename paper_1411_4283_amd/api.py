@@ -71,14 +71,17 @@ _BC = {"dirichlet": _lib.BC_DIRICHLET, "neumann": _lib.BC_NEUMANN}
 
 
 def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = "dirichlet",
-              reuse_templates: bool = False) -> Opts:
+              reuse_templates: bool = False, weight_power: float | None = None) -> Opts:
     """cutcell_opts; eb_bc: "dirichlet" or "neumann" on every embedded-boundary face;
-    reuse_templates: copy the stencils of faces whose systems are bitwise identical."""
+    reuse_templates: copy the stencils of faces whose systems are bitwise identical;
+    weight_power: the exponent p of W = (2d)^-p (None: the paper's 5)."""
     if eb_bc not in _BC:
         raise ValueError(f"eb_bc must be one of {sorted(_BC)}")
     o = Opts()
     o.eb_bc = _BC[eb_bc]
     o.reuse_templates = 1 if reuse_templates else 0
+    o.weight_custom = 0 if weight_power is None else 1
+    o.weight_power = 5.0 if weight_power is None else float(weight_power)
     o.dim = dim
     nn = list(n) + [1] * (3 - len(n))
     for d in range(3):
@@ -193,14 +196,14 @@ class Builder:
     grid, order and path radius, so repeated builds allocate nothing new."""
 
     def __init__(self, geoms, path_radius: int, device="cuda", eb_bc: str = "dirichlet",
-                 reuse_templates: bool = False):
+                 reuse_templates: bool = False, weight_power: float | None = None):
         geoms = list(geoms) if isinstance(geoms, (list, tuple)) else [geoms]
         g0 = geoms[0]
         for g in geoms:
             assert (g.dim, g.n, g.h, g.order) == (g0.dim, g0.n, g0.h, g0.order), "a batch shares its grid"
         self.geoms = geoms
         self.dim = g0.dim
-        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc, reuse_templates)
+        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc, reuse_templates, weight_power)
         self.eb_bc = eb_bc
         self.garr = (Geom * len(geoms))(*[g.struct() for g in geoms])
         lib = load()
@@ -415,6 +418,46 @@ def solve(st: Stencils, phi_bc: torch.Tensor, rhs: torch.Tensor, x0: torch.Tenso
     if rc not in (OK, W_NOT_CONVERGED):
         check(rc, "cutcell_solve", allow_flagged=False)
     return SolveResult(x[: s.n_vol], int(it.value), float(rr.value), rc == OK)
+
+
+def hessenberg_eigs(H) -> "np.ndarray":
+    """Eigenvalues of a square upper Hessenberg matrix (host, cutcell_hessenberg_eigs)."""
+    import numpy as np
+
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = H.shape[0]
+    re = np.zeros(max(n, 1))
+    im = np.zeros(max(n, 1))
+    rc = load().cutcell_hessenberg_eigs(n, H.ctypes.data, H.shape[1], re.ctypes.data, im.ctypes.data)
+    check(rc, "cutcell_hessenberg_eigs", allow_flagged=False)
+    return (re + 1j * im)[:n]
+
+
+def ritz(st: Stencils, mode: int = 0, steps: int = 40, lap: "Laplacian | None" = None, inner_rtol: float = 1e-10,
+         inner_restart: int = 100, inner_max_iters: int = 5000, stream=None):
+    """Ritz values of the volume operator (cutcell_ritz): mode 0 on A (eigenvalues of
+    largest magnitude), mode 1 shift-invert about 0 (those nearest 0).  Returns a complex
+    numpy array and whether every inner solve converged."""
+    import numpy as np
+
+    s = st.sizes
+    lib = load()
+    nbytes = lib.cutcell_ritz_workspace_bytes(ctypes.byref(s), steps, mode, inner_restart)
+    if nbytes == 0:
+        raise ValueError("bad Ritz parameters")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=st.val.device)
+    re = np.zeros(steps)
+    im = np.zeros(steps)
+    nr = ctypes.c_int32(0)
+    arr = st.struct()
+    la = ctypes.byref(lap.struct()) if lap is not None else None
+    rc = lib.cutcell_ritz(ctypes.byref(s), st.dim, ctypes.byref(arr), la, mode, steps, inner_rtol, inner_restart,
+                          inner_max_iters, re.ctypes.data, im.ctypes.data, ctypes.byref(nr), _ptr(ws), nbytes,
+                          _stream(stream))
+    if rc != W_NOT_CONVERGED:
+        check(rc, "cutcell_ritz", allow_flagged=False)
+    k = int(nr.value)
+    return (re + 1j * im)[:k], rc == OK
 
 
 def n_monomials(dim: int, order: int) -> int:

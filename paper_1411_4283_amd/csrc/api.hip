@@ -108,6 +108,10 @@ static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
   if (o->order != 2 && o->order != 4) return fail(CUTCELL_E_UNSUPPORTED, "order must be 2 or 4");
   if (o->path_radius < 1 || o->path_radius > 4) return fail(CUTCELL_E_UNSUPPORTED, "path_radius must be in [1, 4]");
   if (!(o->h > 0)) return fail(CUTCELL_E_INVALID_ARG, "h must be positive");
+  if (o->weight_custom != 0 && o->weight_custom != 1)
+    return fail(CUTCELL_E_INVALID_ARG, "weight_custom must be 0 or 1");
+  if (o->weight_custom && !(o->weight_power >= 0.0 && o->weight_power <= 16.0))
+    return fail(CUTCELL_E_INVALID_ARG, "weight_power must be in [0, 16]");
   if (o->reuse_templates != 0 && o->reuse_templates != 1)
     return fail(CUTCELL_E_INVALID_ARG, "reuse_templates must be 0 or 1");
   if (o->eb_bc != CUTCELL_BC_DIRICHLET && o->eb_bc != CUTCELL_BC_NEUMANN)
@@ -468,6 +472,49 @@ int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
   const int rc = solve_poisson(op, sizes->n_geom, st_->phi_off, st_->vol_off, phi_bc, rhs, x, restart, max_iters,
                                rtol, (char*)workspace, workspace_bytes, &it, relres);
   if (iters) *iters = it;
+  return rc;
+}
+
+int cutcell_hessenberg_eigs(int32_t n, const double* H, int32_t ld, double* re, double* im) {
+  if (n < 0 || ld < n || (n > 0 && (!H || !re || !im))) return fail(CUTCELL_E_INVALID_ARG, "bad arguments");
+  if (n > 4096) return fail(CUTCELL_E_UNSUPPORTED, "n must be at most 4096");
+  if (hessenberg_eigs(n, H, ld, re, im)) return fail(CUTCELL_E_BREAKDOWN, "Hessenberg QR did not converge");
+  return CUTCELL_OK;
+}
+
+size_t cutcell_ritz_workspace_bytes(const cutcell_sizes* sizes, int32_t steps, int32_t mode, int32_t inner_restart) {
+  if (!sizes || steps < 1 || steps > 1024 || (mode != 0 && mode != 1) ||
+      (mode == 1 && (inner_restart < 1 || inner_restart > 1024)))
+    return 0;
+  return ritz_workspace_bytes(sizes->n_vol, sizes->n_phi, sizes->n_face, steps, mode == 1 ? inner_restart : 0);
+}
+
+int cutcell_ritz(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const cutcell_laplacian* lap,
+                 int32_t mode, int32_t steps, double inner_rtol, int32_t inner_restart, int32_t inner_max_iters,
+                 double* ritz_re, double* ritz_im, int32_t* n_ritz, void* workspace, size_t workspace_bytes,
+                 cutcell_stream_t stream) {
+  if (!sizes || !stencils_complete(st_) || !st_->phi_off || !st_->vol_off || !ritz_re || !ritz_im || !n_ritz ||
+      !workspace)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (mode != 0 && mode != 1) return fail(CUTCELL_E_INVALID_ARG, "mode must be 0 or 1");
+  if (steps < 1 || steps > 1024) return fail(CUTCELL_E_INVALID_ARG, "steps must be in [1, 1024]");
+  if (mode == 1 && (inner_restart < 1 || inner_restart > 1024 || inner_max_iters < 1 || !(inner_rtol > 0.0)))
+    return fail(CUTCELL_E_INVALID_ARG, "bad inner solve parameters");
+  if (sizes->n_geom < 1 || sizes->n_vol < 1 || sizes->n_phi >= (1LL << 31)) return fail(CUTCELL_E_INVALID_ARG, "bad sizes");
+  *n_ritz = 0;
+  SolveOp op{dim, sizes->n_vol, sizes->n_phi, sizes->n_face, st_->row_ptr, st_->col, st_->val, st_->vol_face,
+             st_->vol_scale, (hipStream_t)stream};
+  if (lap) {
+    if (!lap->row_ptr || !lap->col || !lap->val) return fail(CUTCELL_E_INVALID_ARG, "lap arrays are NULL");
+    op.lap_ptr = lap->row_ptr;
+    op.lap_col = lap->col;
+    op.lap_val = lap->val;
+  }
+  int nr = 0;
+  const int rc = ritz_values(op, sizes->n_geom, st_->phi_off, st_->vol_off, mode, steps, inner_rtol, inner_restart,
+                             inner_max_iters, ritz_re, ritz_im, nullptr, &nr, (char*)workspace, workspace_bytes);
+  *n_ritz = nr;
   return rc;
 }
 

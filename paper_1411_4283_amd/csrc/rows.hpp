@@ -104,13 +104,16 @@ __device__ __forceinline__ void load_row_moments(const RowSource& rs, double* m)
 }
 
 // Weight of a row at offset delta = (x_i - x0)/h (Sec. 2.4): 1 inside half a cell, else
-// (2 |delta|)^-5.
-__device__ __forceinline__ double row_weight(double d2) {
+// (2 |delta|)^-p, p = 5 in the paper (wpow; other exponents for weight studies).
+__device__ __forceinline__ double row_weight(double d2, double wpow) {
   const double dist = sqrt(d2);
   if (dist < 0.5) return 1.0;
   const double t = 2.0 * dist;
-  const double t2 = t * t;
-  return 1.0 / (t2 * t2 * t);
+  if (wpow == 5.0) {
+    const double t2 = t * t;
+    return 1.0 / (t2 * t2 * t);
+  }
+  return pow(t, -wpow);
 }
 
 }  // namespace cutcell

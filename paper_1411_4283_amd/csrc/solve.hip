@@ -9,6 +9,7 @@
 // All reductions sum per-block partials in a fixed order, so a solve is deterministic.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <string>
 #include <vector>
 
@@ -338,6 +339,180 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
   if (relres_out) *relres_out = res / bnorm;
   if (!std::isfinite(res)) return fail(CUTCELL_E_BREAKDOWN, "GMRES produced a non-finite residual");
   return res <= rtol * bnorm ? CUTCELL_OK : CUTCELL_W_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------------------
+// Extreme eigenvalues of the volume operator A (L restricted to the volume values, the
+// boundary entries of Phi zero) from Arnoldi's method on the GPU (the spectra of
+// Sec. 3.4 / 3.5, at any size).
+
+// Eigenvalues of an n x n upper Hessenberg matrix (row-major, leading dimension ld) by
+// shifted QR iterations in complex arithmetic: Givens rotations reduce the active block
+// minus mu I to triangular form R, the block becomes R Q + mu I, mu is the eigenvalue of
+// its trailing 2 x 2 part nearer the last diagonal entry (Wilkinson's shift, perturbed
+// every 11th step), and the block deflates from the bottom once a subdiagonal entry is
+// below the rounding level of its diagonal neighbours.  Host code.  Returns 0, or -1 if an
+// eigenvalue needs more than 200 steps.
+int hessenberg_eigs(int n, const double* H, int ld, double* re, double* im) {
+  using cd = std::complex<double>;
+  std::vector<cd> a((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) a[(size_t)i * n + j] = (j >= i - 1) ? cd(H[(size_t)i * ld + j], 0.0) : cd(0.0, 0.0);
+  auto A = [&](int i, int j) -> cd& { return a[(size_t)i * n + j]; };
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1, steps = 0;
+  while (hi >= 0) {
+    int lo = hi;
+    while (lo > 0 && std::abs(A(lo, lo - 1)) > eps * (std::abs(A(lo, lo)) + std::abs(A(lo - 1, lo - 1)))) --lo;
+    if (lo > 0) A(lo, lo - 1) = 0.0;
+    if (lo == hi) {
+      re[hi] = A(hi, hi).real();
+      im[hi] = A(hi, hi).imag();
+      --hi;
+      steps = 0;
+      continue;
+    }
+    if (++steps > 200) return -1;
+    const cd a11 = A(hi - 1, hi - 1), a12 = A(hi - 1, hi), a21 = A(hi, hi - 1), a22 = A(hi, hi);
+    const cd half = 0.5 * (a11 + a22);
+    const cd disc = std::sqrt(0.25 * (a11 - a22) * (a11 - a22) + a12 * a21);
+    const cd m1 = half + disc, m2 = half - disc;
+    cd mu = (std::abs(m1 - a22) < std::abs(m2 - a22)) ? m1 : m2;
+    if (steps % 11 == 10) mu = a22 + std::abs(a21);
+    for (int k = lo; k <= hi; ++k) A(k, k) -= mu;
+    std::vector<cd> cs(hi - lo), sn(hi - lo);
+    for (int k = lo; k < hi; ++k) {            // R = Q^H (H - mu I)
+      const cd x = A(k, k), y = A(k + 1, k);
+      const double r = std::hypot(std::abs(x), std::abs(y));
+      const cd c = r > 0.0 ? x / r : cd(1.0, 0.0), s = r > 0.0 ? y / r : cd(0.0, 0.0);
+      cs[k - lo] = c;
+      sn[k - lo] = s;
+      for (int j = k; j <= hi; ++j) {
+        const cd u = A(k, j), v = A(k + 1, j);
+        A(k, j) = std::conj(c) * u + std::conj(s) * v;
+        A(k + 1, j) = -s * u + c * v;
+      }
+    }
+    for (int k = lo; k < hi; ++k) {            // R Q
+      const cd c = cs[k - lo], s = sn[k - lo];
+      for (int i = lo; i <= std::min(k + 1, hi); ++i) {
+        const cd u = A(i, k), v = A(i, k + 1);
+        A(i, k) = c * u + s * v;
+        A(i, k + 1) = -std::conj(s) * u + std::conj(c) * v;
+      }
+    }
+    for (int k = lo; k <= hi; ++k) A(k, k) += mu;
+  }
+  return 0;
+}
+
+// start vector: a fixed pseudo-random vector (splitmix64 of the index) in [-1, 1)
+__global__ void k_start_vector(long long n, double* __restrict__ v) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = (unsigned long long)i + 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  z ^= z >> 31;
+  v[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+size_t ritz_workspace_bytes(long long n_vol, long long n_phi, long long n_face, int k, int inner_m) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t nv = std::max<long long>(n_vol, 1);
+  return al(sizeof(double) * n_phi) * 2 + al(sizeof(double) * std::max<long long>(n_face, 1)) +
+         al(sizeof(double) * nv) + al(sizeof(int32_t) * nv) + al(sizeof(double) * nv * (k + 1)) +
+         al(sizeof(double) * kDotBlocks * (k + 2)) + al(sizeof(double) * coef_words(k)) +
+         (inner_m > 0 ? solve_workspace_bytes(n_vol, n_phi, n_face, inner_m) : 0);
+}
+
+int ritz_values(const SolveOp& op, int G, const int64_t* phi_off, const int64_t* vol_off, int mode, int k,
+                double inner_rtol, int inner_m, int inner_max, double* ritz_re, double* ritz_im, double* hess,
+                int* n_out, char* ws, size_t ws_bytes) {
+  const long long n = op.n_vol;
+  if (ws_bytes < ritz_workspace_bytes(n, op.n_phi, op.n_face, k, mode == 1 ? inner_m : 0))
+    return fail(CUTCELL_E_WORKSPACE, "Ritz workspace too small");
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t off = 0;
+  auto take = [&](size_t bytes) { char* p = ws + off; off += al(bytes); return p; };
+  const size_t nv = std::max<long long>(n, 1);
+  double* zero_bc = (double*)take(sizeof(double) * op.n_phi);   // Phi = 0 (the inner solves' data)
+  double* phi0 = (double*)take(sizeof(double) * op.n_phi);      // [v | 0]
+  double* flux = (double*)take(sizeof(double) * std::max<long long>(op.n_face, 1));
+  double* w = (double*)take(sizeof(double) * nv);
+  int32_t* vphi = (int32_t*)take(sizeof(int32_t) * nv);
+  double* V = (double*)take(sizeof(double) * nv * (k + 1));
+  double* partial = (double*)take(sizeof(double) * kDotBlocks * (k + 2));
+  double* cbuf = (double*)take(sizeof(double) * coef_words(k));
+  char* inner_ws = ws + off;
+  double* c1 = cbuf;
+  double* c2 = cbuf + (k + 1);
+  double* hnb = cbuf + (k + 1) + (k + 2);
+  std::vector<double> hc(coef_words(k));
+  hipStream_t st = op.st;
+  const int T = 256;
+  const unsigned gv = nb(n, T);
+  auto mdot = [&](int kk, int self, const double* y, double* out) {
+    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(kDotBlock), 0, st, n, kk, self, V, y, partial);
+    hipLaunchKernelGGL(k_mdot_final, dim3(kk + self), dim3(kDotBlock), 0, st, partial, out);
+  };
+  hipLaunchKernelGGL(k_vol_phi, dim3(gv), dim3(T), 0, st, n, G, phi_off, vol_off, vphi);
+  hipLaunchKernelGGL(k_fill_f64, dim3(nb(op.n_phi, T)), dim3(T), 0, st, phi0, op.n_phi, 0.0);
+  hipLaunchKernelGGL(k_fill_f64, dim3(nb(op.n_phi, T)), dim3(T), 0, st, zero_bc, op.n_phi, 0.0);
+  hipLaunchKernelGGL(k_start_vector, dim3(gv), dim3(T), 0, st, n, V);
+  double n2 = 0.0;
+  mdot(0, 1, V, hnb);
+  CC_HIP(hipMemcpyAsync(&n2, hnb, sizeof(double), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipStreamSynchronize(st));
+  hipLaunchKernelGGL(k_axpby, dim3(gv), dim3(T), 0, st, n, 1.0 / std::sqrt(n2), V, 0.0, V, V);
+  std::vector<double> Hm((size_t)(k + 1) * k, 0.0);
+  int kk = k, inner_fail = 0;
+  for (int j = 0; j < k; ++j) {
+    double* vj = V + (long long)j * n;
+    double* vn = V + (long long)(j + 1) * n;
+    if (mode == 0) {
+      hipLaunchKernelGGL(k_scatter, dim3(gv), dim3(T), 0, st, n, vphi, vj, phi0);
+      int rc = op.lap_ptr ? apply_laplacian(op.D, n, op.lap_ptr, op.lap_col, op.lap_val, phi0, w, st)
+                          : apply_operator(op.D, op.n_face, n, op.row_ptr, op.col, op.val, op.vol_face,
+                                           op.vol_scale, phi0, w, flux, nullptr, st);
+      if (rc) return rc;
+    } else {
+      hipLaunchKernelGGL(k_fill_f64, dim3(gv), dim3(T), 0, st, w, n, 0.0);
+      int it = 0;
+      double rr = 0.0;
+      const int rc = solve_poisson(op, G, phi_off, vol_off, zero_bc, vj, w, inner_m, inner_max, inner_rtol, inner_ws,
+                                   solve_workspace_bytes(n, op.n_phi, op.n_face, inner_m), &it, &rr);
+      if (rc == CUTCELL_W_NOT_CONVERGED) inner_fail = 1;
+      else if (rc) return rc;
+    }
+    mdot(j + 1, 0, w, c1);
+    hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j + 1, c1, V, w);
+    mdot(j + 1, 1, w, c2);
+    hipLaunchKernelGGL(k_maxpy, dim3(gv), dim3(T), 0, st, n, j + 1, c2, V, w);
+    hipLaunchKernelGGL(k_norm_after, dim3(1), dim3(1), 0, st, c2, j + 1, hnb);
+    hipLaunchKernelGGL(k_scale_dev, dim3(gv), dim3(T), 0, st, n, w, hnb, vn);
+    CC_HIP(hipMemcpyAsync(hc.data(), cbuf, sizeof(double) * coef_words(k), hipMemcpyDeviceToHost, st));
+    CC_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i <= j; ++i) Hm[(size_t)i * k + j] = hc[i] + hc[(k + 1) + i];
+    const double hn = hc[(k + 1) + (k + 2)];
+    Hm[(size_t)(j + 1) * k + j] = hn;
+    if (!(hn > 0.0)) {       // invariant subspace: its eigenvalues are exact
+      kk = j + 1;
+      break;
+    }
+  }
+  CC_HIP(hipGetLastError());
+  if (hess)
+    for (size_t i = 0; i < Hm.size(); ++i) hess[i] = Hm[i];
+  if (hessenberg_eigs(kk, Hm.data(), k, ritz_re, ritz_im)) return fail(CUTCELL_E_BREAKDOWN, "Hessenberg QR did not converge");
+  if (mode == 1)                // eigenvalues of A^-1: invert
+    for (int i = 0; i < kk; ++i) {
+      const double a = ritz_re[i], b = ritz_im[i], d = a * a + b * b;
+      ritz_re[i] = d > 0.0 ? a / d : 0.0;
+      ritz_im[i] = d > 0.0 ? -b / d : 0.0;
+    }
+  *n_out = kk;
+  return inner_fail ? CUTCELL_W_NOT_CONVERGED : CUTCELL_OK;
 }
 
 }  // namespace cutcell

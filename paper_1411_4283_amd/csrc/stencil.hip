@@ -47,7 +47,7 @@ __device__ __forceinline__ double recip_f64(double d) {
 // moments m (overwritten) and centre; returns its weight in w, and false if the row
 // holds a non-finite value.
 template <int D, int Q>
-__device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h, double* m, double& w) {
+__device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h, double* m, double& w, double wpow) {
   constexpr int M = Dims<D, Q>::M;
   double delta[3] = {0, 0, 0};
   double d2 = 0;
@@ -55,7 +55,7 @@ __device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h,
     delta[ax] = ctr[ax] - x0h[ax];
     d2 += delta[ax] * delta[ax];
   }
-  w = row_weight(d2);
+  w = row_weight(d2, wpow);
   const double mu0 = m[0];
   recentre<D, Q>(m, delta);
   const double sc = w / mu0;
@@ -73,7 +73,7 @@ __device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h,
 // `ctr` and re-centred to x0 like the other rows.  Returns false on a non-finite value.
 template <int D, int Q>
 __device__ __forceinline__ bool neumann_row(const GeomPtrs& gp, int32_t e, const double* ctr, const double* x0h,
-                                            double* m, double& w) {
+                                            double* m, double& w, double wpow) {
   constexpr int M = Dims<D, Q>::M, M1 = Dims<D, Q>::M1;
   double delta[3] = {0, 0, 0};
   double d2 = 0;
@@ -81,7 +81,7 @@ __device__ __forceinline__ bool neumann_row(const GeomPtrs& gp, int32_t e, const
     delta[ax] = ctr[ax] - x0h[ax];
     d2 += delta[ax] * delta[ax];
   }
-  w = row_weight(d2);
+  w = row_weight(d2, wpow);
   const double sc = w / gp.eb_mom[(long long)e * M];
   static_for<0, M>([&](auto I) { m[I] = 0.0; });
   static_for<0, D>([&](auto AX) {
@@ -217,7 +217,7 @@ template <int D, int Q, int NPAD, bool NEU = false>
 __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
                                             const int32_t* __restrict__ vol_cell, const int32_t* __restrict__ box_lf,
                                             const int32_t* __restrict__ col, FaceSmem<D, Q, NPAD>& sm, int lane,
-                                            double* a, double& sdiag) {
+                                            double* a, double& sdiag, double wpow) {
   using DM = Dims<D, Q>;
   constexpr int M = DM::M, MT = DM::MT, MS = DM::MS;
   double* Bs = sm.Bs;
@@ -243,14 +243,14 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       if (r < N) {
         if constexpr (NEU) {
           if (rsrc[R].eb >= 0) {
-            finite = neumann_row<D, Q>(gp, rsrc[R].eb, rsrc[R].ctr, fi.x0h, m, wr) && finite;
+            finite = neumann_row<D, Q>(gp, rsrc[R].eb, rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
           } else {
             load_row_moments<D, Q>(rsrc[R], m);
-            finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr) && finite;
+            finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
           }
         } else {
           load_row_moments<D, Q>(rsrc[R], m);
-          finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr) && finite;
+          finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
         }
       } else {
         static_for<0, M>([&](auto I) { m[I] = 0.0; });
@@ -431,6 +431,7 @@ struct StencilArgs {
   int xcd;
   int per_xcd;
   double h;            // grid spacing (Neumann rows carry one more power of h)
+  double wpow;         // weight exponent p of W = (2 |delta|)^-p
 };
 
 // Faces of a bin taken by workgroup blockIdx.x in turn (-1 when done).  With xcd = 1 and a
@@ -483,7 +484,7 @@ __device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, 
   double sdiag;
   const int st = face_forward<D, Q, NPAD, NEU>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
                                                A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a,
-                                               sdiag);
+                                               sdiag, A.wpow);
   for (int r = lane; r < fi.N; r += 64) {
     double v = (st == CUTCELL_STATUS_OK) ? A.hscale * sm.wls[r] * sm.zs[r] : 0.0;
     if constexpr (NEU) {
@@ -565,7 +566,7 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
     if (lane < 4) og[lane] = 0.0;
     return;
   }
-  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag);
+  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag, A.wpow);
   const double* Bs = sm.Bs;
   if (st != CUTCELL_STATUS_OK) {   // a flagged face has s = 0 whatever its inputs: no gradient
     for (int r = lane; r < N; r += 64) {
@@ -634,7 +635,7 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
     B.nz_rz[2 * (fi.rp + r) + 1] = W * zz;
     if (fi.kind == 1) {
       // delta_i = x_i/h - x0h: d B_ip / d delta_d = p_d B_i,p-e_d (weight fixed), and
-      // dW/d delta_d = -5 W delta_d / |delta|^2 outside half a cell
+      // dW/d delta_d = -p W delta_d / |delta|^2 outside half a cell (W = (2|delta|)^-p)
       const RowSource rs = row_source<D, Q>(A.g, gp, (int64_t)A.col[fi.rp + r] - fi.phi0, fi.n_vol, fi.n_eb,
                                             vol_cell, box_lf);
       double dl[3] = {0, 0, 0}, d2 = 0.0;
@@ -657,7 +658,7 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
         });
       });
       if (sqrt(d2) >= 0.5)
-        for (int ax = 0; ax < D; ++ax) gd[ax] += wtot * (-5.0 * W * dl[ax] / d2);
+        for (int ax = 0; ax < D; ++ax) gd[ax] += wtot * (-A.wpow * W * dl[ax] / d2);
       for (int ax = 0; ax < D; ++ax) gx[ax] -= gd[ax];   // d delta / d x0h = -1
     }
   }
@@ -797,6 +798,7 @@ static StencilArgs stencil_args(const Work& w, double hscale, const int32_t* per
   A.row_ptr = row_ptr;
   A.col = col;
   A.h = 0.0;
+  A.wpow = 5.0;
   return A;
 }
 
@@ -828,9 +830,10 @@ struct BinSchedule {
 template <int D, int Q, int NPAD>
 static void launch_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, const int64_t* row_ptr,
                        const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
-                       BinSchedule sc, bool neu, double h) {
+                       BinSchedule sc, bool neu, double h, double wpow) {
   if (nbin <= 0) return;
   StencilArgs A = stencil_args(w, hscale, perm, nbin, row_ptr, col);
+  A.wpow = wpow;
   if (bw) {
     hipLaunchKernelGGL((k_stencil_backward<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, A, *bw);
     return;
@@ -858,7 +861,7 @@ static void launch_bin(const Work& w, double hscale, const int32_t* perm, long l
 template <int D, int Q>
 static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count, const int64_t* row_ptr,
                          const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
-                         const BinSchedule* sched, int only_bin, bool neu, double h) {
+                         const BinSchedule* sched, int only_bin, bool neu, double h, double wpow) {
   constexpr int M = binom(Q + D, D);
   long long start = 0;
   for (int b = 0; b < kMaxBins; ++b) {
@@ -869,14 +872,14 @@ static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count,
     const int npad = kBinRows * (b + 1);
     if (npad < M) return fail(CUTCELL_E_INVALID_ARG, "internal: face with N >= M in a bin narrower than M");
     switch (npad) {
-      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
-      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h); break;
+      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
+      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
     }
   }
   const long long ninsuf = (only_bin < 0) ? bin_count[kMaxBins] : 0;
@@ -903,7 +906,7 @@ static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_cou
 #define CC_RB(DD, QQ) \
   if (o.dim == DD && o.order == QQ) \
     return dispatch_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin, \
-                                 o.eb_bc == CUTCELL_BC_NEUMANN, o.h);
+                                 o.eb_bc == CUTCELL_BC_NEUMANN, o.h, o.weight_custom ? o.weight_power : 5.0);
   CC_RB(2, 2) CC_RB(2, 4) CC_RB(3, 2) CC_RB(3, 4)
 #undef CC_RB
   return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");

@@ -1,0 +1,194 @@
+"""Weight-function study (cutcell_opts.weight_custom / weight_power: W = (2d)^-p beyond half
+a cell; the paper's p = 5, Sec. 2.4) and the GPU Arnoldi spectra (cutcell_ritz).
+
+* Stencils and their adjoint at other exponents against the oracle (same bars as p = 5).
+* Ritz values against the dense eigenvalues of the oracle's operator (32 x 32 circle).
+* The paper's spectra on the 64 x 64 circle (Sec. 3.4 / 3.5 table): lambda_max -104
+  (Dirichlet) and -38 (Neumann); lambda_min within a factor 2; the unweighted operator
+  (p = 0) has positive eigenvalues; the 64^3 sphere operator is stable at scale.
+* d loss / d p from the stencil adjoint's weight gradient against central differences of
+  GPU builds at p +- delta.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import cutgeom as cg
+import oracle
+from oracle import stencils as S
+
+torch = pytest.importorskip("torch")
+import paper_1411_4283_amd as cc  # noqa: E402
+from test_gpu_adjoint import _cmp, _face_subset, _val_bar  # noqa: E402
+from test_gpu_parity import _host  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+CIRCLE = cg.ball_outside((0.5, 0.5), 0.25)
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _build(g, R, **kw):
+    dg = cc.DeviceGeometry.from_host(g, DEV)
+    b = cc.Builder(dg, R, **kw)
+    st = b.build()
+    torch.cuda.synchronize()
+    return dg, b, st
+
+
+@pytest.mark.parametrize("p", [0.0, 3.0, 7.5])
+def test_weight_power_stencils_match_oracle(p):
+    g = cg.make_geometry(CIRCLE, 32, 4)
+    dg, b, st = _build(g, 3, weight_power=p)
+    en, rp, col, val, status = oracle.build(g, 3, wpow=p)
+    rp_g, col_g, val_g, st_g = _host(st)
+    assert np.array_equal(rp_g, rp) and np.array_equal(col_g, col) and np.array_equal(st_g, status)
+    worst = 0.0
+    for f in range(en.n_face):
+        a, e = rp[f], rp[f + 1]
+        if status[f] != oracle.STATUS_OK:
+            continue
+        err = np.abs(val_g[a:e] - val[a:e]).max() / np.abs(val[a:e]).max()
+        if err > 1e-11:
+            cond = oracle.face_condition(g, en, f, 3, wpow=p)
+            assert err <= 1e-11 * cond / 1e5, (f, err, cond)
+        worst = max(worst, err)
+    _say(f"p = {p}: {en.n_face} faces, worst stencil rel err {worst:.2e}")
+
+
+def test_weight_power_adjoint_matches_oracle():
+    g = cg.make_geometry(CIRCLE, 16, 4)
+    dg, b, st = _build(g, 3, weight_power=3.0)
+    en = oracle.enumerate_geometry(g)
+    rp = st.row_ptr.cpu().numpy()
+    faces = _face_subset(en, 160, 21)
+    vb = _val_bar(rp, faces, int(st.sizes.nnz), 22)
+    grads, wb = b.backward(st, torch.from_numpy(vb).to(DEV), weight_bar=True)
+    torch.cuda.synchronize()
+    G = oracle.stencils_backward(g, en, 3, rp, vb, faces=faces, wpow=3.0)
+    gg = grads[0]
+    _cmp("vol_mom p=3", gg["vol_mom"].cpu().numpy(), G["vol_mom"])
+    for d in range(2):
+        _cmp(f"face_mom[{d}] p=3", gg["face_mom"][d].cpu().numpy(), G["face_mom"][d])
+    _cmp("eb_mom p=3", gg["eb_mom"].cpu().numpy(), G["eb_mom"])
+    _cmp("eb_nmom p=3", gg["eb_nmom"].cpu().numpy(), G["eb_nmom"])
+    _cmp("weight p=3", wb.cpu().numpy(), G["weight"])
+
+
+def _nearest(ev, z):
+    return float(np.min(np.abs(np.asarray(ev) - z)))
+
+
+@pytest.mark.parametrize("p", [5.0, 0.0])
+def test_ritz_values_match_dense_eigenvalues(p):
+    g = cg.make_geometry(CIRCLE, 32, 4)
+    dg, b, st = _build(g, 3, weight_power=p)
+    en, rp, col, val, status = oracle.build(g, 3, wpow=p)
+    A = oracle.operator_matrix(g, en, rp, col, val)[:, : en.n_vol].toarray()
+    ev = np.linalg.eigvals(A)
+    r0, ok0 = cc.ritz(st, mode=0, steps=80)
+    r1, ok1 = cc.ritz(st, mode=1, steps=30, inner_rtol=1e-13)
+    assert ok0 and ok1
+    lmin = ev[np.argmin(ev.real)]
+    near0 = ev[np.argmin(np.abs(ev))]
+    _say(f"p = {p}: dense lambda_min {lmin:.6g}, nearest 0 {near0:.6g}, max Re {ev.real.max():.6g}; "
+         f"Ritz min Re {r0.real.min():.6g}, nearest 0 {r1[np.argmin(np.abs(r1))]:.6g}, max Re {r0.real.max():.6g}")
+    # the extreme Ritz values are eigenvalues of the dense operator (the two operators differ
+    # by the stencil bar, 1e-11 relative)
+    assert _nearest(ev, r0[np.argmin(r0.real)]) <= 1e-6 * abs(lmin)
+    assert _nearest(ev, r1[np.argmin(np.abs(r1))]) <= 1e-6 * abs(near0)
+    assert abs(r0.real.min() - lmin.real) <= 1e-6 * abs(lmin)
+    assert abs(r1[np.argmin(np.abs(r1))] - near0) <= 1e-6 * abs(near0)
+    if p == 0.0:   # unweighted least squares: unstable (Sec. 3.4)
+        assert ev.real.max() > 1e3 and max(r0.real.max(), r1.real.max()) > 1e3
+
+
+@pytest.mark.parametrize("bc,lam_max,lam_min", [("dirichlet", -104.0, -9.5e6), ("neumann", -38.0, -6.9e4)])
+def test_paper_spectra_64(bc, lam_max, lam_min):
+    g = cg.make_geometry(CIRCLE, 64, 4)
+    dg, b, st = _build(g, 3, eb_bc=bc)
+    r1, ok1 = cc.ritz(st, mode=1, steps=30, inner_rtol=1e-12)
+    r0, ok0 = cc.ritz(st, mode=0, steps=80)
+    assert ok0 and ok1
+    lmax = max(r1.real.max(), r0.real.max())
+    lmin = r0.real.min()
+    _say(f"64^2 {bc}: lambda_max {lmax:.2f} (paper {lam_max}), lambda_min {lmin:.3e} (paper {lam_min:.1e})")
+    assert abs(lmax - lam_max) < 3.0
+    assert lam_min * 2.0 <= lmin <= lam_min / 2.0
+
+
+def test_sphere64_operator_is_stable_at_scale():
+    """The 64^3 workload (236k volumes): the eigenvalue nearest 0 and the most negative
+    one, through the volume matrix."""
+    g = cg.make_geometry(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 64, 4)
+    dg, b, st = _build(g, 3)
+    lap = cc.build_laplacian(st)
+    r1, ok1 = cc.ritz(st, mode=1, steps=20, lap=lap, inner_rtol=1e-10)
+    r0, ok0 = cc.ritz(st, mode=0, steps=60, lap=lap)
+    assert ok0 and ok1
+    lmax = max(r1.real.max(), r0.real.max())
+    _say(f"sphere64: lambda_max {lmax:.3f}, lambda_min {r0.real.min():.3e}")
+    assert lmax < 0.0
+    # Dirichlet eigenvalues grow when the domain shrinks: the unit cube minus the ball has
+    # -lambda_1 above the full cube's 3 pi^2 (2 % allowed for the discretisation)
+    assert lmax < -0.98 * 3 * math.pi**2
+
+
+def _loss_setup(g, en):
+    tp = 2 * math.pi
+    I = g.integrate(cg.trig_product((tp, tp), (-tp * math.sqrt(2) / 2, -tp * math.sqrt(3) / 2)))
+    hD, hD1 = g.h**2, g.h
+    vol = en.vol_cell
+    box = np.array([I["face_int"][d][f] / (g.face_mom[d][f, 0] * hD1) for d, f in zip(en.box_dir, en.box_face)])
+    phi = np.concatenate([I["vol_int"][vol] / (g.kappa[vol] * hD), I["eb_int"] / (g.eb_mom[:, 0] * hD1), box])
+    f = I["vol_lap"][vol] / (g.kappa[vol] * hD)
+    return phi, f, g.kappa[vol]
+
+
+def _loss(st, phi_t, f, kap):
+    L, _ = cc.apply(st, phi_t)
+    r = kap * (L.cpu().numpy() - f)
+    return float(np.sum(r * r)), r
+
+
+def test_exponent_gradient_by_finite_differences():
+    """loss = sum_v (kappa_v (L_v - f_v))^2 with Phi, f from the paper's 2D exact solution;
+    d loss / d p = sum_i (d loss / d W_i) (d W_i / d p), d W_i / d p = -ln(2 d_i) W_i beyond
+    half a cell, from cutcell_stencils_backward's weight gradient."""
+    p = 5.0
+    g = cg.make_geometry(CIRCLE, 32, 4)
+    en = oracle.enumerate_geometry(g)
+    phi, f, kap = _loss_setup(g, en)
+    phi_t = torch.from_numpy(phi).to(DEV)
+    dg, b, st = _build(g, 3, weight_power=p)
+    l0, r = _loss(st, phi_t, f, kap)
+    lbar = torch.from_numpy(2.0 * kap * r).to(DEV)
+    _, val_bar, _, _ = cc.apply_adjoint(st, lbar, phi=phi_t)
+    _, wb = b.backward(st, val_bar.contiguous(), weight_bar=True)
+    wb = wb.cpu().numpy()
+    rp = st.row_ptr.cpu().numpy()
+    dW = np.zeros_like(wb)
+    for fc in range(en.n_face):
+        A, W, F, idx = S.face_system(g, en, fc, 3, wpow=p)
+        x0 = S.face_centre(en, fc)
+        d = np.sqrt(np.sum(((en.row_ctr[idx] - x0) / en.h) ** 2, axis=1))
+        dW[rp[fc]:rp[fc + 1]] = np.where(d >= 0.5, -np.log(2.0 * np.maximum(d, 0.5)) * W, 0.0)
+    grad = float(np.dot(wb, dW))
+
+    def loss_at(q):
+        _, _, s = _build(g, 3, weight_power=q)
+        assert torch.equal(s.status, st.status)
+        return _loss(s, phi_t, f, kap)[0]
+
+    def central(h):
+        return (loss_at(p + h) - loss_at(p - h)) / (2 * h)
+
+    fd = (4 * central(1e-3) - central(2e-3)) / 3
+    _say(f"d loss / d p at p = 5: adjoint {grad:.9e}, finite differences {fd:.9e} (loss {l0:.6e})")
+    assert abs(grad - fd) <= 1e-6 * abs(fd)
