@@ -128,6 +128,27 @@ def test_stencil_minimises_weighted_norm(case, request):
         assert np.linalg.norm(resid) <= 64 * np.finfo(float).eps * cond * np.linalg.norm(z)
 
 
+@pytest.mark.parametrize("wpow", [0.0, 2.5, 8.0])
+def test_weight_exponent_keeps_the_minimum_norm_characterisation(wpow):
+    """With W = (2d)^-p for another exponent p (Sec. 2.4 fixes p = 5), the stencil is still
+    the solution of A^T s = F of least ||W^-1 s||: W^-1 s lies in the range of W A, and
+    A^T s = F holds; the weights themselves are (2d)^-p beyond half a cell."""
+    g = cg.make_geometry(CIRCLE, 16, 4)
+    en = oracle.enumerate_geometry(g)
+    for f in range(0, en.n_face, 9):
+        A, W, F, idx = oracle.face_system(g, en, f, 3, wpow=wpow)
+        d = np.sqrt(np.sum(((en.row_ctr[idx] - S.face_centre(en, f)) / en.h) ** 2, axis=1))
+        assert np.allclose(W, np.where(d < 0.5, 1.0, (2 * np.maximum(d, 0.5)) ** -wpow), rtol=1e-15, atol=0)
+        idx2, val, status = oracle.face_stencil(g, en, f, 3, wpow=wpow)
+        assert status == oracle.STATUS_OK
+        s = val / g.h ** (g.D - 2)
+        assert np.abs(A.T @ s - F).max() <= 1e-10 * max(np.abs(A.T).dot(np.abs(s)).max(), 1.0)
+        z = s / W
+        U, sv, _ = np.linalg.svd(W[:, None] * A, full_matrices=False)
+        resid = z - U @ (U.T @ z)
+        assert np.linalg.norm(resid) <= 64 * np.finfo(float).eps * sv[0] / sv[-1] * np.linalg.norm(z)
+
+
 def test_stencil_against_exact_solve(c1):
     """The stencil equals W^2 A (A^T W^2 A)^-1 F computed in 40-digit arithmetic from the
     same (exactly representable) inputs, to within cond * eps."""
