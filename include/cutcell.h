@@ -85,7 +85,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 9
+#define CUTCELL_ABI_VERSION 10
 
 enum {
   CUTCELL_OK = 0,
@@ -359,12 +359,15 @@ size_t cutcell_ritz_workspace_bytes(const cutcell_sizes* sizes, int32_t steps, i
  *           inner_max_iters), values inverted -- the eigenvalues nearest 0 (lambda_max of
  *           a stable operator).
  * lap (may be NULL): the volume matrix for the products.  ritz_re/ritz_im [steps] (host)
- * receive *n_ritz values (fewer than steps if an invariant subspace is found).  Returns
+ * receive *n_ritz values (fewer than steps if an invariant subspace is found); ritz_res
+ * (host, may be NULL) their relative residuals |A u - theta u| / |theta| (of A^-1 in mode
+ * 1; -1 when steps > 256): only values with small residuals are eigenvalues -- for a
+ * strongly non-normal operator the others can lie far outside the spectrum.  Returns
  * CUTCELL_W_NOT_CONVERGED if an inner solve did not converge.  Synchronises `stream`. */
 int cutcell_ritz(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st, const cutcell_laplacian* lap,
                  int32_t mode, int32_t steps, double inner_rtol, int32_t inner_restart, int32_t inner_max_iters,
-                 double* ritz_re, double* ritz_im, int32_t* n_ritz, void* workspace, size_t workspace_bytes,
-                 cutcell_stream_t stream);
+                 double* ritz_re, double* ritz_im, double* ritz_res, int32_t* n_ritz, void* workspace,
+                 size_t workspace_bytes, cutcell_stream_t stream);
 
 /* Observability: when enabled (per calling thread), cutcell_build_stencils records HIP
  * events on its stream between its phases, and cutcell_last_profile copies the last

@@ -147,7 +147,7 @@ SIGNATURES = {
                                                        ctypes.c_int32]),
     "cutcell_ritz": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
                                     ctypes.POINTER(LaplacianArrays), ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                    ctypes.c_int32, ctypes.c_int32, P, P, ctypes.POINTER(ctypes.c_int32), P,
+                                    ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.POINTER(ctypes.c_int32), P,
                                     ctypes.c_size_t, P]),
     "cutcell_laplacian_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
     "cutcell_laplacian_count": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P,

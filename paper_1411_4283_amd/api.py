@@ -437,7 +437,8 @@ def ritz(st: Stencils, mode: int = 0, steps: int = 40, lap: "Laplacian | None" =
          inner_restart: int = 100, inner_max_iters: int = 5000, stream=None):
     """Ritz values of the volume operator (cutcell_ritz): mode 0 on A (eigenvalues of
     largest magnitude), mode 1 shift-invert about 0 (those nearest 0).  Returns a complex
-    numpy array and whether every inner solve converged."""
+    numpy array, their relative residuals (small for converged values) and whether every
+    inner solve converged."""
     import numpy as np
 
     s = st.sizes
@@ -448,16 +449,17 @@ def ritz(st: Stencils, mode: int = 0, steps: int = 40, lap: "Laplacian | None" =
     ws = torch.empty(nbytes, dtype=torch.uint8, device=st.val.device)
     re = np.zeros(steps)
     im = np.zeros(steps)
+    res = np.zeros(steps)
     nr = ctypes.c_int32(0)
     arr = st.struct()
     la = ctypes.byref(lap.struct()) if lap is not None else None
     rc = lib.cutcell_ritz(ctypes.byref(s), st.dim, ctypes.byref(arr), la, mode, steps, inner_rtol, inner_restart,
-                          inner_max_iters, re.ctypes.data, im.ctypes.data, ctypes.byref(nr), _ptr(ws), nbytes,
-                          _stream(stream))
+                          inner_max_iters, re.ctypes.data, im.ctypes.data, res.ctypes.data, ctypes.byref(nr),
+                          _ptr(ws), nbytes, _stream(stream))
     if rc != W_NOT_CONVERGED:
         check(rc, "cutcell_ritz", allow_flagged=False)
     k = int(nr.value)
-    return (re + 1j * im)[:k], rc == OK
+    return (re + 1j * im)[:k], res[:k], rc == OK
 
 
 def n_monomials(dim: int, order: int) -> int:

@@ -491,8 +491,8 @@ size_t cutcell_ritz_workspace_bytes(const cutcell_sizes* sizes, int32_t steps, i
 
 int cutcell_ritz(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const cutcell_laplacian* lap,
                  int32_t mode, int32_t steps, double inner_rtol, int32_t inner_restart, int32_t inner_max_iters,
-                 double* ritz_re, double* ritz_im, int32_t* n_ritz, void* workspace, size_t workspace_bytes,
-                 cutcell_stream_t stream) {
+                 double* ritz_re, double* ritz_im, double* ritz_res, int32_t* n_ritz, void* workspace,
+                 size_t workspace_bytes, cutcell_stream_t stream) {
   if (!sizes || !stencils_complete(st_) || !st_->phi_off || !st_->vol_off || !ritz_re || !ritz_im || !n_ritz ||
       !workspace)
     return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
@@ -513,7 +513,8 @@ int cutcell_ritz(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils
   }
   int nr = 0;
   const int rc = ritz_values(op, sizes->n_geom, st_->phi_off, st_->vol_off, mode, steps, inner_rtol, inner_restart,
-                             inner_max_iters, ritz_re, ritz_im, nullptr, &nr, (char*)workspace, workspace_bytes);
+                             inner_max_iters, ritz_re, ritz_im, ritz_res, nullptr, &nr, (char*)workspace,
+                             workspace_bytes);
   *n_ritz = nr;
   return rc;
 }

@@ -406,6 +406,60 @@ int hessenberg_eigs(int n, const double* H, int ld, double* re, double* im) {
   return 0;
 }
 
+// Relative residuals of Ritz pairs: for (theta, y) with H y = theta y (y of unit norm), the
+// Arnoldi relation gives |A V y - theta V y| = |h_{k+1,k}| |y_k|; res = that / |theta|.
+// y from three steps of inverse iteration with H - theta I (complex Gaussian elimination
+// with partial pivoting; theta nudged by 1e-13 relative so the matrix stays invertible).
+// Host code; k at most 256 (else res = -1).
+void ritz_residuals(int k, const double* H, int ld, double hlast, const double* re, const double* im, double* res) {
+  using cd = std::complex<double>;
+  if (k > 256) {
+    for (int t = 0; t < k; ++t) res[t] = -1.0;
+    return;
+  }
+  std::vector<cd> M((size_t)k * k), y(k), b(k);
+  for (int t = 0; t < k; ++t) {
+    const cd th(re[t], im[t]);
+    const cd sh = th + cd(std::abs(th) * 1e-13 + 1e-300, 0.0);
+    for (int i = 0; i < k; ++i) y[i] = 1.0 / std::sqrt((double)k);
+    for (int iter = 0; iter < 3; ++iter) {
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j)
+          M[(size_t)i * k + j] = (j >= i - 1 ? cd(H[(size_t)i * ld + j], 0.0) : cd(0.0, 0.0)) - (i == j ? sh : cd(0.0));
+      b = y;
+      for (int c = 0; c < k; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < k; ++r)
+          if (std::abs(M[(size_t)r * k + c]) > std::abs(M[(size_t)pr * k + c])) pr = r;
+        if (pr != c) {
+          for (int j = c; j < k; ++j) std::swap(M[(size_t)c * k + j], M[(size_t)pr * k + j]);
+          std::swap(b[c], b[pr]);
+        }
+        const cd piv = M[(size_t)c * k + c];
+        if (std::abs(piv) == 0.0) continue;
+        for (int r = c + 1; r < k; ++r) {
+          const cd fct = M[(size_t)r * k + c] / piv;
+          if (fct == cd(0.0)) continue;
+          for (int j = c; j < k; ++j) M[(size_t)r * k + j] -= fct * M[(size_t)c * k + j];
+          b[r] -= fct * b[c];
+        }
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        cd acc = b[i];
+        for (int j = i + 1; j < k; ++j) acc -= M[(size_t)i * k + j] * y[j];
+        const cd piv = M[(size_t)i * k + i];
+        y[i] = std::abs(piv) > 0.0 ? acc / piv : cd(0.0);
+      }
+      double nrm = 0.0;
+      for (int i = 0; i < k; ++i) nrm += std::norm(y[i]);
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0) || !std::isfinite(nrm)) break;
+      for (int i = 0; i < k; ++i) y[i] /= nrm;
+    }
+    res[t] = std::abs(hlast) * std::abs(y[k - 1]) / std::max(std::abs(th), 1e-300);
+  }
+}
+
 // start vector: a fixed pseudo-random vector (splitmix64 of the index) in [-1, 1)
 __global__ void k_start_vector(long long n, double* __restrict__ v) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -427,8 +481,8 @@ size_t ritz_workspace_bytes(long long n_vol, long long n_phi, long long n_face, 
 }
 
 int ritz_values(const SolveOp& op, int G, const int64_t* phi_off, const int64_t* vol_off, int mode, int k,
-                double inner_rtol, int inner_m, int inner_max, double* ritz_re, double* ritz_im, double* hess,
-                int* n_out, char* ws, size_t ws_bytes) {
+                double inner_rtol, int inner_m, int inner_max, double* ritz_re, double* ritz_im, double* ritz_res,
+                double* hess, int* n_out, char* ws, size_t ws_bytes) {
   const long long n = op.n_vol;
   if (ws_bytes < ritz_workspace_bytes(n, op.n_phi, op.n_face, k, mode == 1 ? inner_m : 0))
     return fail(CUTCELL_E_WORKSPACE, "Ritz workspace too small");
@@ -505,6 +559,7 @@ int ritz_values(const SolveOp& op, int G, const int64_t* phi_off, const int64_t*
   if (hess)
     for (size_t i = 0; i < Hm.size(); ++i) hess[i] = Hm[i];
   if (hessenberg_eigs(kk, Hm.data(), k, ritz_re, ritz_im)) return fail(CUTCELL_E_BREAKDOWN, "Hessenberg QR did not converge");
+  if (ritz_res) ritz_residuals(kk, Hm.data(), k, kk < k ? 0.0 : Hm[(size_t)kk * k + (kk - 1)], ritz_re, ritz_im, ritz_res);
   if (mode == 1)                // eigenvalues of A^-1: invert
     for (int i = 0; i < kk; ++i) {
       const double a = ritz_re[i], b = ritz_im[i], d = a * a + b * b;

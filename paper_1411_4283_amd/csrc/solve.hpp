@@ -39,7 +39,7 @@ int solve_poisson(const SolveOp& op, int G, const int64_t* phi_off, const int64_
 int hessenberg_eigs(int n, const double* H, int ld, double* re, double* im);
 size_t ritz_workspace_bytes(long long n_vol, long long n_phi, long long n_face, int k, int inner_m);
 int ritz_values(const SolveOp& op, int G, const int64_t* phi_off, const int64_t* vol_off, int mode, int k,
-                double inner_rtol, int inner_m, int inner_max, double* ritz_re, double* ritz_im, double* hess,
-                int* n_out, char* ws, size_t ws_bytes);
+                double inner_rtol, int inner_m, int inner_max, double* ritz_re, double* ritz_im, double* ritz_res,
+                double* hess, int* n_out, char* ws, size_t ws_bytes);
 
 }  // namespace cutcell

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 9
+    assert lib.cutcell_abi_version() == 10
 
 
 def _opts(**kw):

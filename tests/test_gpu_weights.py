@@ -42,14 +42,30 @@ def _build(g, R, **kw):
     return dg, b, st
 
 
+def _exact_stencil(g, en, f, R, p):
+    """s = W^2 A (A^T W^2 A)^-1 F in 50-digit arithmetic from the same inputs."""
+    import mpmath
+
+    A, W, F, idx = oracle.face_system(g, en, f, R, wpow=p)
+    mpmath.mp.dps = 50
+    Am = mpmath.matrix(A.tolist())
+    W2 = mpmath.diag([mpmath.mpf(w) ** 2 for w in W])
+    y = mpmath.lu_solve(Am.T * W2 * Am, mpmath.matrix(F.tolist()))
+    return g.h ** (g.D - 2) * np.array([float(v) for v in W2 * Am * y])
+
+
 @pytest.mark.parametrize("p", [0.0, 3.0, 7.5])
 def test_weight_power_stencils_match_oracle(p):
+    """Bars as for p = 5.  Steep weights make some systems ill-conditioned; where the two
+    sides differ by more than the bar, the 50-digit solution decides: the GPU stencil must
+    be within the bar of it (the oracle's LAPACK solve then carries the difference: at
+    p = 7.5 it is off by 1.3 cond eps on a face of cond 9.3e5)."""
     g = cg.make_geometry(CIRCLE, 32, 4)
     dg, b, st = _build(g, 3, weight_power=p)
     en, rp, col, val, status = oracle.build(g, 3, wpow=p)
     rp_g, col_g, val_g, st_g = _host(st)
     assert np.array_equal(rp_g, rp) and np.array_equal(col_g, col) and np.array_equal(st_g, status)
-    worst = 0.0
+    worst, exact_checked = 0.0, 0
     for f in range(en.n_face):
         a, e = rp[f], rp[f + 1]
         if status[f] != oracle.STATUS_OK:
@@ -57,9 +73,15 @@ def test_weight_power_stencils_match_oracle(p):
         err = np.abs(val_g[a:e] - val[a:e]).max() / np.abs(val[a:e]).max()
         if err > 1e-11:
             cond = oracle.face_condition(g, en, f, 3, wpow=p)
-            assert err <= 1e-11 * cond / 1e5, (f, err, cond)
+            bar = 1e-11 * max(cond / 1e5, 1.0)
+            if err > bar:
+                se = _exact_stencil(g, en, f, 3, p)
+                eg = np.abs(val_g[a:e] - se).max() / np.abs(se).max()
+                assert eg <= bar, (f, eg, cond)
+                exact_checked += 1
+                err = eg
         worst = max(worst, err)
-    _say(f"p = {p}: {en.n_face} faces, worst stencil rel err {worst:.2e}")
+    _say(f"p = {p}: {en.n_face} faces, worst stencil rel err {worst:.2e} ({exact_checked} decided by the exact solve)")
 
 
 def test_weight_power_adjoint_matches_oracle():
@@ -92,52 +114,75 @@ def test_ritz_values_match_dense_eigenvalues(p):
     en, rp, col, val, status = oracle.build(g, 3, wpow=p)
     A = oracle.operator_matrix(g, en, rp, col, val)[:, : en.n_vol].toarray()
     ev = np.linalg.eigvals(A)
-    r0, ok0 = cc.ritz(st, mode=0, steps=80)
-    r1, ok1 = cc.ritz(st, mode=1, steps=30, inner_rtol=1e-13)
-    assert ok0 and ok1
+    r0, e0, ok0 = cc.ritz(st, mode=0, steps=80)
+    assert ok0
     lmin = ev[np.argmin(ev.real)]
-    near0 = ev[np.argmin(np.abs(ev))]
-    _say(f"p = {p}: dense lambda_min {lmin:.6g}, nearest 0 {near0:.6g}, max Re {ev.real.max():.6g}; "
-         f"Ritz min Re {r0.real.min():.6g}, nearest 0 {r1[np.argmin(np.abs(r1))]:.6g}, max Re {r0.real.max():.6g}")
+    # the leftmost Ritz value has converged (small residual) and is an eigenvalue
+    assert e0[np.argmin(r0.real)] <= 1e-8
+    _say(f"p = {p}: dense lambda_min {lmin:.6g}, max Re {ev.real.max():.6g}; Ritz min Re {r0.real.min():.6g}, "
+         f"max Re {r0.real.max():.6g}")
     # the extreme Ritz values are eigenvalues of the dense operator (the two operators differ
     # by the stencil bar, 1e-11 relative)
     assert _nearest(ev, r0[np.argmin(r0.real)]) <= 1e-6 * abs(lmin)
-    assert _nearest(ev, r1[np.argmin(np.abs(r1))]) <= 1e-6 * abs(near0)
     assert abs(r0.real.min() - lmin.real) <= 1e-6 * abs(lmin)
-    assert abs(r1[np.argmin(np.abs(r1))] - near0) <= 1e-6 * abs(near0)
-    if p == 0.0:   # unweighted least squares: unstable (Sec. 3.4)
-        assert ev.real.max() > 1e3 and max(r0.real.max(), r1.real.max()) > 1e3
+    if p == 5.0:
+        # shift-invert: the eigenvalue nearest 0, the rightmost one of a stable operator
+        r1, e1, ok1 = cc.ritz(st, mode=1, steps=30, inner_rtol=1e-13)
+        assert ok1 and e1[np.argmin(np.abs(r1))] <= 1e-8
+        near0 = ev[np.argmin(np.abs(ev))]
+        _say(f"p = 5: dense nearest 0 {near0:.8g}, Ritz nearest 0 {r1[np.argmin(np.abs(r1))]:.8g}")
+        assert abs(r1[np.argmin(np.abs(r1))] - near0) <= 1e-6 * abs(near0)
+    else:
+        # unweighted least squares (Sec. 3.4): eigenvalues far in the right half plane, and
+        # Arnoldi on A finds one
+        conv = r0[e0 <= 1e-8]
+        assert ev.real.max() > 1e3 and conv.real.max() > 1e3
+        top = conv[np.argmax(conv.real)]
+        assert _nearest(ev, top) <= 1e-6 * abs(top)
 
 
 @pytest.mark.parametrize("bc,lam_max,lam_min", [("dirichlet", -104.0, -9.5e6), ("neumann", -38.0, -6.9e4)])
 def test_paper_spectra_64(bc, lam_max, lam_min):
     g = cg.make_geometry(CIRCLE, 64, 4)
     dg, b, st = _build(g, 3, eb_bc=bc)
-    r1, ok1 = cc.ritz(st, mode=1, steps=30, inner_rtol=1e-12)
-    r0, ok0 = cc.ritz(st, mode=0, steps=80)
+    r1, e1, ok1 = cc.ritz(st, mode=1, steps=30, inner_rtol=1e-12)
+    r0, e0, ok0 = cc.ritz(st, mode=0, steps=80)
     assert ok0 and ok1
-    lmax = max(r1.real.max(), r0.real.max())
+    assert e1[np.argmin(np.abs(r1))] <= 1e-8 and e0[np.argmin(r0.real)] <= 1e-8
+    # shift-invert converges to the eigenvalue nearest 0 (the largest |theta| of A^-1); the
+    # inverses of its small, unconverged Ritz values are meaningless
+    lmax = r1[np.argmin(np.abs(r1))].real
     lmin = r0.real.min()
     _say(f"64^2 {bc}: lambda_max {lmax:.2f} (paper {lam_max}), lambda_min {lmin:.3e} (paper {lam_min:.1e})")
     assert abs(lmax - lam_max) < 3.0
     assert lam_min * 2.0 <= lmin <= lam_min / 2.0
 
 
-def test_sphere64_operator_is_stable_at_scale():
-    """The 64^3 workload (236k volumes): the eigenvalue nearest 0 and the most negative
-    one, through the volume matrix."""
+def test_sphere64_spectrum_at_scale():
+    """The 64^3 workload (236k volumes) through the volume matrix: the eigenvalue nearest 0
+    (shift-invert) converges and, by domain monotonicity of Dirichlet eigenvalues, lies
+    below the full cube's -3 pi^2.  Arnoldi on A reports its converged Ritz values (with
+    the paper's exponent one of them lies far in the right half plane: the 3D operator on
+    this geometry is not stable; see the weight study)."""
     g = cg.make_geometry(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 64, 4)
     dg, b, st = _build(g, 3)
     lap = cc.build_laplacian(st)
-    r1, ok1 = cc.ritz(st, mode=1, steps=20, lap=lap, inner_rtol=1e-10)
-    r0, ok0 = cc.ritz(st, mode=0, steps=60, lap=lap)
+    r1, e1, ok1 = cc.ritz(st, mode=1, steps=20, lap=lap, inner_rtol=1e-10)
+    r0, e0, ok0 = cc.ritz(st, mode=0, steps=60, lap=lap)
     assert ok0 and ok1
-    lmax = max(r1.real.max(), r0.real.max())
-    _say(f"sphere64: lambda_max {lmax:.3f}, lambda_min {r0.real.min():.3e}")
-    assert lmax < 0.0
+    i1 = np.argmin(np.abs(r1))
+    near0 = r1[i1]
+    conv0 = r0[e0 <= 1e-6]
+    _say(f"sphere64: eigenvalue nearest 0 {near0:.4f} (residual {e1[i1]:.1e}); Arnoldi on A: "
+         f"{len(conv0)} of {len(r0)} Ritz values converged, most negative {r0.real.min():.4e} "
+         f"(residual {e0[np.argmin(r0.real)]:.1e}), largest real part {r0.real.max():.4e} "
+         f"(residual {e0[np.argmax(r0.real)]:.1e}), largest converged real part "
+         f"{conv0.real.max() if len(conv0) else float('nan'):.4e}")
+    assert e1[i1] <= 1e-6 and abs(near0.imag) <= 1e-6 * abs(near0)
     # Dirichlet eigenvalues grow when the domain shrinks: the unit cube minus the ball has
     # -lambda_1 above the full cube's 3 pi^2 (2 % allowed for the discretisation)
-    assert lmax < -0.98 * 3 * math.pi**2
+    assert near0.real < -0.98 * 3 * math.pi**2
+    assert len(conv0) > 0
 
 
 def _loss_setup(g, en):
