@@ -400,7 +400,7 @@ def spectrum_at_scale(cc, st, lap):
                       "60 steps on A for the most negative"}
 
 
-def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=200, lap=None):
+def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=50, lap=None):
     """The discrete Poisson problem on the workload's geometry (Dirichlet data and source
     from the paper's 3D exact solution, Sec. 3.6) solved by the GPU GMRES (cutcell_solve);
     wall-clock time of the call, iterations, and the solution error against the exact

@@ -392,7 +392,7 @@ class SolveResult:
 
 
 def solve(st: Stencils, phi_bc: torch.Tensor, rhs: torch.Tensor, x0: torch.Tensor | None = None,
-          restart: int = 200, max_iters: int = 5000, rtol: float = 1e-10, stream=None,
+          restart: int = 50, max_iters: int = 5000, rtol: float = 1e-10, stream=None,
           lap: "Laplacian | None" = None) -> SolveResult:
     """Solve L([x | bc]) = rhs for the volume values x (cutcell_solve: restarted GMRES with
     right Jacobi preconditioning on the GPU).  `phi_bc` holds the boundary data in its EB

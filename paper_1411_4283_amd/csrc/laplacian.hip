@@ -179,7 +179,7 @@ int apply_laplacian(int D, long long n_vol, const int64_t* lap_ptr, const int32_
   if (n_vol <= 0) return CUTCELL_OK;
   const int T = 256;
   if (D == 3) {
-    constexpr int F = 2, U = 5;   // ~129 entries per regular volume
+    constexpr int F = 4, U = 10;  // ~129 entries per regular volume (the fastest shape measured)
     const long long waves = (n_vol + F - 1) / F;
     hipLaunchKernelGGL((k_flux<F, U>), dim3((unsigned)((waves * 64 + T - 1) / T)), dim3(T), 0, st, n_vol, lap_ptr,
                        lap_col, lap_val, phi, lphi);
