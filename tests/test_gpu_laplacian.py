@@ -136,3 +136,37 @@ def test_laplacian_full_size_apply_and_solve():
     e2 = np.abs(r2.x.cpu().numpy() - ph[: en.n_vol]).max() / np.abs(ph).max()
     _say(f"quartic solve: face path {r1.iters} it, err {e1:.2e}; matrix {r2.iters} it, err {e2:.2e}")
     assert e2 <= 1e-8 and abs(r1.iters - r2.iters) <= 0.05 * r1.iters + 2
+
+
+def test_laplacian_and_solve_on_a_batch():
+    """Two geometries in one build: the volume matrix of the batch is the two matrices one
+    after the other (bit for bit), and one solve of the batch gives each geometry's
+    solution of its own problem (to the solver tolerance)."""
+    from test_gpu_solve import _exact_phi_and_rhs, _t
+    shapes = [cg.ball_outside((0.5, 0.5), 0.25), cg.ball_outside((0.47, 0.52), 0.27)]
+    gs = [cg.make_geometry(sh, 32, 4) for sh in shapes]
+    dgs = [cc.DeviceGeometry.from_host(g, DEV) for g in gs]
+    both = cc.Builder(dgs, 3).build()
+    lap = cc.build_laplacian(both)
+    singles = [cc.Builder(d, 3).build() for d in dgs]
+    laps = [cc.build_laplacian(s_) for s_ in singles]
+    torch.cuda.synchronize()
+    assert lap.nnz == sum(l_.nnz for l_ in laps)
+    assert torch.equal(lap.val[: lap.nnz], torch.cat([l_.val[: l_.nnz] for l_ in laps]))
+    off = singles[0].sizes.n_phi
+    assert torch.equal(lap.col[: laps[0].nnz], laps[0].col[: laps[0].nnz])
+    assert torch.equal(lap.col[laps[0].nnz: lap.nnz], laps[1].col[: laps[1].nnz] + off)
+    tp = 2 * math.pi
+    field = cg.trig_product((tp, tp), (-tp * math.sqrt(2) / 2, -tp * math.sqrt(3) / 2))
+    parts = [_exact_phi_and_rhs(g, oracle.enumerate_geometry(g), field) for g in gs]
+    n0 = singles[0].sizes.n_vol
+    # batch Phi: each geometry's [volumes | EB | box] block in turn; rhs: volumes in turn
+    phi = np.concatenate([p[0] for p in parts])
+    rhs = np.concatenate([p[1] for p in parts])
+    rb = cc.solve(both, _t(phi), _t(rhs), rtol=1e-13, lap=lap)
+    r0 = cc.solve(singles[0], _t(parts[0][0]), _t(parts[0][1]), rtol=1e-13, lap=laps[0])
+    r1 = cc.solve(singles[1], _t(parts[1][0]), _t(parts[1][1]), rtol=1e-13, lap=laps[1])
+    assert rb.converged and r0.converged and r1.converged
+    xb = rb.x.cpu().numpy()
+    for xs, part in ((r0.x.cpu().numpy(), xb[:n0]), (r1.x.cpu().numpy(), xb[n0:])):
+        assert np.abs(xs - part).max() <= 1e-8 * np.abs(xs).max()
