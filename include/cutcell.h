@@ -68,6 +68,9 @@
  *    exact derivatives (up to rounding).  For a scalar loss l, *_bar denotes dl/d(.).
  *    Results are deterministic: no floating-point atomics, fixed summation orders.
  *
+ *  Empty inputs.  A batch may have no fluid at all (no volumes, no faces): the build
+ *    then writes only offsets, and cutcell_apply, cutcell_apply_laplacian and cutcell_solve
+ *    return CUTCELL_OK at once, accepting NULL for the arrays whose sizes are zero.
  *  Errors.  Every entry point returns CUTCELL_OK (0), CUTCELL_W_FLAGGED_FACES (> 0:
  *    success, some faces got a nonzero status) or a negative CUTCELL_E_* code; the
  *    message of the last error on the calling thread is cutcell_last_error().  The

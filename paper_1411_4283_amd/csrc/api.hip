@@ -221,9 +221,12 @@ static int count_rows(const Prepared& P, const cutcell_opts* o, int64_t* row_ptr
     if (rc) return rc;
   }
   int32_t mr = 0;
+  const int64_t zero = 0;
   CC_HIP(hipMemcpyAsync(&mr, w.bins + 2 * kNBuckets, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   if (row_ptr && P.n_face > 0)
     CC_HIP(hipMemcpyAsync(&total, row_ptr + P.n_face, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  else if (row_ptr)   // no faces: row_ptr = [0]
+    CC_HIP(hipMemcpyAsync(row_ptr, &zero, sizeof(int64_t), hipMemcpyHostToDevice, st));
   CC_HIP(hipStreamSynchronize(st));
   *nnz = total;
   *maxrows = mr;
@@ -401,8 +404,10 @@ int cutcell_last_profile(double* ms, int32_t n) {
 
 int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const double* phi,
                   double* lphi, double* flux, cutcell_stream_t stream) {
-  if (!sizes || !st_ || !phi || !lphi || !flux) return fail(CUTCELL_E_INVALID_ARG, "NULL argument (flux is required)");
+  if (!sizes) return fail(CUTCELL_E_INVALID_ARG, "sizes is NULL");
   if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (sizes->n_vol == 0 && sizes->n_face == 0) return CUTCELL_OK;   // nothing to apply (arrays may be NULL)
+  if (!st_ || !phi || !lphi || !flux) return fail(CUTCELL_E_INVALID_ARG, "NULL argument (flux is required)");
   if (!st_->row_ptr || !st_->col || !st_->val || !st_->vol_face || !st_->vol_scale)
     return fail(CUTCELL_E_INVALID_ARG, "stencil arrays are NULL");
   return apply_operator(dim, sizes->n_face, sizes->n_vol, st_->row_ptr, st_->col, st_->val, st_->vol_face,
@@ -440,21 +445,29 @@ int cutcell_laplacian_fill(const cutcell_sizes* sizes, int32_t dim, const cutcel
 
 int cutcell_apply_laplacian(const cutcell_sizes* sizes, int32_t dim, const cutcell_laplacian* lap, const double* phi,
                             double* lphi, cutcell_stream_t stream) {
-  if (!sizes || !lap || !lap->row_ptr || !lap->col || !lap->val || !phi || !lphi)
-    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (!sizes) return fail(CUTCELL_E_INVALID_ARG, "sizes is NULL");
   if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (sizes->n_vol == 0) return CUTCELL_OK;   // nothing to apply (arrays may be NULL)
+  if (!lap || !lap->row_ptr || !lap->col || !lap->val || !phi || !lphi)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
   return apply_laplacian(dim, sizes->n_vol, lap->row_ptr, lap->col, lap->val, phi, lphi, (hipStream_t)stream);
 }
 
 int cutcell_solve(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_, const cutcell_laplacian* lap,
                   const double* phi_bc, const double* rhs, double* x, int32_t restart, int32_t max_iters, double rtol,
                   void* workspace, size_t workspace_bytes, int32_t* iters, double* relres, cutcell_stream_t stream) {
-  if (!sizes || !stencils_complete(st_) || !st_->phi_off || !st_->vol_off || !phi_bc || !rhs || !x || !workspace)
-    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (!sizes) return fail(CUTCELL_E_INVALID_ARG, "sizes is NULL");
   if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
   if (restart < 1 || restart > 1024) return fail(CUTCELL_E_INVALID_ARG, "restart must be in [1, 1024]");
   if (max_iters < 0) return fail(CUTCELL_E_INVALID_ARG, "max_iters must be >= 0");
   if (!(rtol >= 0.0)) return fail(CUTCELL_E_INVALID_ARG, "rtol must be >= 0");
+  if (sizes->n_vol == 0) {   // nothing to solve (arrays may be NULL)
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return CUTCELL_OK;
+  }
+  if (!stencils_complete(st_) || !st_->phi_off || !st_->vol_off || !phi_bc || !rhs || !x || !workspace)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
   if (sizes->n_geom < 1 || sizes->n_vol < 0 || sizes->n_phi >= (1LL << 31))
     return fail(CUTCELL_E_INVALID_ARG, "bad sizes");
   if (iters) *iters = 0;

@@ -107,8 +107,15 @@ def test_build_and_apply_reject_null_outputs(lib):
     st = _lib.StencilArrays()
     assert lib.cutcell_build_stencils(ctypes.byref(g), 1, ctypes.byref(o), ctypes.byref(sizes), ctypes.byref(st),
                                       None, 0, None) == _lib.E_INVALID_ARG
-    assert lib.cutcell_apply(ctypes.byref(sizes), 3, ctypes.byref(st), None, None, None, None) == _lib.E_INVALID_ARG
     assert lib.cutcell_apply(ctypes.byref(sizes), 4, ctypes.byref(st), 8, 8, 8, None) == _lib.E_UNSUPPORTED
+    # an empty batch (no volumes, no faces) needs no arrays at all
+    assert lib.cutcell_apply(ctypes.byref(sizes), 3, None, None, None, None, None) == _lib.OK
+    it = ctypes.c_int32(-1)
+    assert lib.cutcell_solve(ctypes.byref(sizes), 3, None, None, None, None, None, 10, 10, 1e-8, None, 0,
+                             ctypes.byref(it), None, None) == _lib.OK and it.value == 0
+    full = _lib.Sizes(n_vol=10, n_eb=0, n_box=4, n_phi=14, n_face=20, nnz=100, max_rows=5, n_geom=1)
+    assert lib.cutcell_apply(ctypes.byref(full), 3, ctypes.byref(st), None, None, None, None) == _lib.E_INVALID_ARG
+    assert lib.cutcell_apply_laplacian(ctypes.byref(full), 3, None, None, None, None) == _lib.E_INVALID_ARG
 
 
 def _fake_stencils():
