@@ -431,7 +431,22 @@ def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=50, lap=None):
     ms = (time.perf_counter() - t0) * 1e3
     e = res.x.cpu().numpy() - phi[: len(vols)]
     V = kap[vols] * hD
+    # algorithmic bytes of the Arnoldi steps: the matvec (the volume matrix's or the face
+    # path's bytes) and, at Krylov index j, two Gram-Schmidt passes each reading j+1 basis
+    # vectors twice (inner products, update) and w three times, plus the scaling of D^-1 v
+    n = len(vols)
+    s = st.sizes
+    mv = (12 * lap.nnz + 8 * (n + 1) + 8 * s.n_phi + 8 * n) if lap is not None else \
+        (12 * s.nnz + 8 * (s.n_face + 1) + 8 * s.n_phi + 16 * n)
+    steps_bytes = 0
+    for it in range(res.iters):
+        j = it % restart
+        steps_bytes += mv + 2 * (8 * n * 2 * (j + 1) + 8 * n * 3) + 8 * n * 5
+    gbs = steps_bytes / (ms * 1e-3) / 1e9
     return {"ms": ms, "iterations": res.iters, "ms_per_iteration": ms / max(res.iters, 1), "relres": res.relres,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS, "bytes": steps_bytes,
+                         "note": "algorithmic bytes of all Arnoldi steps over the whole solve time"},
             "converged": res.converged, "rtol": rtol, "restart": restart,
             "apply_share": res.iters * apply_ms / ms, "n_vol": int(len(vols)),
             "error_Linf": float(np.abs(e).max()), "error_L1": float(np.sum(np.abs(e) * V) / V.sum()),
@@ -489,7 +504,22 @@ def cpu_baseline(g, R, sample, seed=7, workers=None):
         out["all_cores"] = dict(value=done / tw, unit="faces/s", cores=workers,
                                 sample=f"{done} faces (seed {seed + 1}) over {workers} processes, {tw:.1f} s; "
                                        "enumeration not included")
+    out["host"] = host_info()
     return out
+
+
+def host_info():
+    """The host the oracle ran on: logical CPUs and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"logical_cpus": os.cpu_count(), "cpu_model": model}
 
 
 def main():
