@@ -86,6 +86,11 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   t.ref_cell = (int32_t*)take(sizeof(int32_t) * G);
   t.tface = (int32_t*)take(sizeof(int32_t) * 3 * G);
   t.tmpl = (int32_t*)take(sizeof(int32_t) * totface);
+  t.okey = (unsigned long long*)take(sizeof(unsigned long long) * totface);
+  t.okey_out = (unsigned long long*)take(sizeof(unsigned long long) * totface);
+  t.oval = (int32_t*)take(sizeof(int32_t) * totface);
+  t.osort_bytes = order_temp_bytes(totface);
+  t.osort_tmp = take(t.osort_bytes);
   t.counts = (int64_t*)take(sizeof(int64_t) * 4 * G);
   t.offs = (int64_t*)take(sizeof(int64_t) * 3 * (G + 1));
   t.fcode = (int32_t*)take(sizeof(int32_t) * totface);

@@ -581,12 +581,6 @@ int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, i
 // faces with fewer rows than monomials; perm lists faces bucket by bucket
 
 // per-block histograms in LDS, one global atomic per bucket per block
-__device__ __forceinline__ int face_bucket(long long f, int M, const int32_t* nrows, const int32_t* tmpl) {
-  if (tmpl && tmpl[f] >= 0) return kMaxBins + 1;
-  const int N = nrows[f];
-  return (N < M) ? kMaxBins : min((N - 1) / kBinRows, kMaxBins - 1);
-}
-
 __global__ __launch_bounds__(256) void k_bin_count(long long n_face, int M, const int32_t* __restrict__ nrows,
                                                    const int32_t* __restrict__ tmpl, int32_t* bins) {
   __shared__ int32_t h[kNBuckets];
@@ -605,25 +599,6 @@ __global__ void k_bin_starts(int32_t* bins) {
     bins[kNBuckets + b] = s;
     s += bins[b];
   }
-}
-
-// each block ranks its faces per bucket in LDS, then reserves one range per bucket
-__global__ __launch_bounds__(256) void k_bin_scatter(long long n_face, int M, const int32_t* __restrict__ nrows,
-                                                     const int32_t* __restrict__ tmpl, int32_t* bins, int32_t* perm) {
-  __shared__ int32_t h[kNBuckets];
-  __shared__ int32_t base[kNBuckets];
-  if (threadIdx.x < kNBuckets) h[threadIdx.x] = 0;
-  __syncthreads();
-  long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  int b = -1, r = 0;
-  if (f < n_face) {
-    b = face_bucket(f, M, nrows, tmpl);
-    r = atomicAdd(&h[b], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x < kNBuckets) base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&bins[kNBuckets + threadIdx.x], h[threadIdx.x]) : 0;
-  __syncthreads();
-  if (b >= 0) perm[base[b] + r] = (int32_t)f;
 }
 
 // largest row count (block reduction, one atomic per block)
@@ -660,10 +635,8 @@ int bin_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hipSt
   if (n_face <= 0) return CUTCELL_OK;
   hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, tmpl, w.bins);
   hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, st, w.bins);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, tmpl,
-                     w.bins, w.perm);
   CC_HIP(hipGetLastError());
-  return CUTCELL_OK;
+  return order_faces(w, n_face, M, tmpl, st);
 }
 
 // ---------------------------------------------------------------------------------------

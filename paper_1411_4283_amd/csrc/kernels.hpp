@@ -38,6 +38,11 @@ struct Work {
   int32_t* ref_cell;    // [G]         the reference (ball-regular) cell, or INT32_MAX
   int32_t* tface;       // [G][3]      template face per direction, or INT32_MAX
   int32_t* tmpl;        // [G*maxface] template of each face whose stencil is copied, else -1
+  unsigned long long* okey;      // [G*maxface] processing-order keys (bucket, then cell)
+  unsigned long long* okey_out;  // [G*maxface]
+  int32_t* oval;        // [G*maxface] face ids to sort
+  char* osort_tmp;      // radix-sort scratch
+  size_t osort_bytes;
   int64_t* counts;      // [G][4]      n_vol, n_eb, n_box, n_gface
   int64_t* offs;        // [3][G+1]    phi_off, vol_off, face_off
   int32_t* fcode;       // [G*maxface] per global flux face
@@ -93,6 +98,16 @@ int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, i
 // binning by row count and the stencil solves (Sec. 2.2.1)
 // `tmpl` (or null): faces with tmpl >= 0 go to the template-copy bucket
 int bin_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hipStream_t st);
+// processing order: faces grouped by bucket, inside a bucket by the cell they sit at
+size_t order_temp_bytes(long long n_items);
+int order_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hipStream_t st);
+
+// bucket of face f: a 16-row bin, the faces with fewer rows than monomials, or the copies
+__host__ __device__ inline int face_bucket(long long f, int M, const int32_t* nrows, const int32_t* tmpl) {
+  if (tmpl && tmpl[f] >= 0) return kMaxBins + 1;
+  const int N = nrows[f];
+  return (N < M) ? kMaxBins : ((N - 1) / kBinRows < kMaxBins - 1 ? (N - 1) / kBinRows : kMaxBins - 1);
+}
 // faces whose systems are bitwise those of one solved face per (geometry, direction)
 int find_templates(const Work& w, const cutcell_opts& o, long long n_face, hipStream_t st);
 int max_rows(const Work& w, long long n_face, hipStream_t st);
