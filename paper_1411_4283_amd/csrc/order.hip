@@ -1,15 +1,19 @@
 // Processing order of the faces (the permutation the stencil kernels walk).  Faces are
 // grouped by bucket (16-row bins, then faces with fewer rows than monomials, then template
-// copies) and, inside a bucket, ordered by the cell they sit at -- a grid face's low-side
+// copies), a row bin's lower half (at most 8 rows above the bin below) first, and inside
+// that ordered by the cell they sit at -- a grid face's low-side
 // cell (the last cell for faces on the high box side), an EB face's cut cell -- so that
 // the faces of all directions around the same cells are solved together and share the
-// rows' moments in one L2.  One stable 64-bit radix sort of (bucket, geometry, cell).
+// rows' moments in one L2.  One stable 64-bit radix sort of (bucket, half, geometry, cell).
 // The stencils do not depend on the order.
 #include <hipcub/hipcub.hpp>
 
 #include "kernels.hpp"
 
 namespace cutcell {
+
+constexpr int kKeyBits = 45;   // 40 bits of (geometry, cell), 5 of (bucket, half)
+static_assert(2 * kNBuckets <= 32, "bucket and half must fit in 5 key bits");
 
 __global__ void k_face_keys(GridDims g, long long n_face, int M, const int32_t* __restrict__ fcode,
                             const int32_t* __restrict__ fref, const GeomPtrs* __restrict__ geoms,
@@ -29,8 +33,9 @@ __global__ void k_face_keys(GridDims g, long long n_face, int M, const int32_t* 
   } else {
     cell = geoms[gi].eb_cell[fref[f]];
   }
-  const unsigned long long b = (unsigned long long)face_bucket(f, M, nrows, tmpl);
-  keys[f] = (b << 40) | (unsigned long long)((long long)gi * g.ncell + cell);
+  const int b = face_bucket(f, M, nrows, tmpl);
+  const unsigned long long bh = ((unsigned long long)b << 1) | (face_lower_half(b, f, nrows) ? 0ull : 1ull);
+  keys[f] = (bh << 40) | (unsigned long long)((long long)gi * g.ncell + cell);
   vals[f] = (int32_t)f;
 }
 
@@ -39,7 +44,7 @@ size_t order_temp_bytes(long long n_items) {
   if (n_items > 0)
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, temp, (const unsigned long long*)nullptr,
                                              (unsigned long long*)nullptr, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                             (int)n_items, 0, 44, (hipStream_t)0);
+                                             (int)n_items, 0, kKeyBits, (hipStream_t)0);
   return temp;
 }
 
@@ -50,8 +55,8 @@ int order_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hip
   hipLaunchKernelGGL(k_face_keys, dim3((unsigned)((n_face + T - 1) / T)), dim3(T), 0, st, w.dims, n_face, M, w.fcode,
                      w.fref, w.geoms, w.nrows, tmpl, w.okey, w.oval);
   size_t bytes = w.osort_bytes;
-  CC_HIP(hipcub::DeviceRadixSort::SortPairs(w.osort_tmp, bytes, w.okey, w.okey_out, w.oval, w.perm, (int)n_face, 0, 44,
-                                            st));
+  CC_HIP(hipcub::DeviceRadixSort::SortPairs(w.osort_tmp, bytes, w.okey, w.okey_out, w.oval, w.perm, (int)n_face, 0,
+                                            kKeyBits, st));
   CC_HIP(hipGetLastError());
   return CUTCELL_OK;
 }

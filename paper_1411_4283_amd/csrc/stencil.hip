@@ -1,747 +1,9 @@
-// Per-face weighted least-squares flux stencils (Sec. 2.2.1, eq. 'stencil equation
-// solution'; neighbours, centring and weights of Sec. 2.4).
-//
-// The stencil s~ = W (A~^T W)^+ F~ is W z with z the minimum-norm solution of
-// B^T z = F~, B = W A~ (N x M, N >= M, full column rank): z = B (B^T B)^-1 F~.  One
-// wavefront owns one face:
-//   1. rows: each lane builds its row(s) of B in registers -- the row's moments,
-//      re-centred to x0 by the binomial theorem, divided by the zeroth moment and
-//      scaled by the weight -- and stores them in LDS;
-//   2. G = B^T B on the FP64 matrix cores (v_mfma_f64_16x16x4f64, 16 x 16 tiles of the
-//      upper triangle, rows of B as the contraction index);
-//   3. G is equilibrated to unit diagonal and inverted by symmetric Gauss-Jordan sweeps,
-//      lane i holding row i in registers; the sweep pivots are the Cholesky pivots;
-//   4. z from the semi-normal equations z = B G^-1 F~ followed by two steps of
-//      refinement with the residual F~ - B^T z computed from B itself, which brings the
-//      error down to that of a backward-stable solve (cond(B) * eps);
-//   5. val = h^(D-2) W z.
-// Under Neumann EB conditions (a separate kernel instance) the EB rows are the
-// normal-derivative rows of eq. 'Neu moment eq for cp' and their values carry h^(D-1);
-// the EB faces themselves have a one-entry stencil (their area) and are written by
-// k_insufficient, the kernel of faces with fewer rows than monomials.
-// Status: fewer rows than monomials, a pivot square root below 1e-7 times the largest after
-// equilibration (numerically rank deficient), or a non-finite entry flag the face.
-#include <algorithm>
-
-#include "kernels.hpp"
-#include "rows.hpp"
+// Host side of the stencil solves: launches per bin (the kernels are in stencil_impl.hpp,
+// instantiated per dimension and order in stencil_d*q*.hip), the faces with fewer rows
+// than monomials, the template copies, and the launch-schedule autotuner.
+#include "stencil_impl.hpp"
 
 namespace cutcell {
-
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-constexpr double kRankTol = 1e-7;
-constexpr int kRefine = 2;
-
-// 1/d from v_rcp_f64 and two Newton steps (each squares the relative error)
-__device__ __forceinline__ double recip_f64(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
-
-
-// One row of B = W A~ about x0 (in units of h: x0h = x0 / h) from the row's stored
-// moments m (overwritten) and centre; returns its weight in w, and false if the row
-// holds a non-finite value.
-template <int D, int Q>
-__device__ __forceinline__ bool finish_row(const double* ctr, const double* x0h, double* m, double& w, double wpow) {
-  constexpr int M = Dims<D, Q>::M;
-  double delta[3] = {0, 0, 0};
-  double d2 = 0;
-  for (int ax = 0; ax < D; ++ax) {
-    delta[ax] = ctr[ax] - x0h[ax];
-    d2 += delta[ax] * delta[ax];
-  }
-  w = row_weight(d2, wpow);
-  const double mu0 = m[0];
-  recentre<D, Q>(m, delta);
-  const double sc = w / mu0;
-  bool finite = isfinite(sc);
-  static_for<0, M>([&](auto I) {
-    m[I] *= sc;
-    finite = finite && isfinite(m[I]);
-  });
-  return finite;
-}
-
-// Neumann row of EB face e about x0 (eq. 'Neu moment eq for cp'): the flux of each
-// monomial xi^p through the face, sum_d p_d nu_d^(p - e_d)(x0), over the face area m^0,
-// times the row's weight.  The normal moments are stored about the cut cell's centre
-// `ctr` and re-centred to x0 like the other rows.  Returns false on a non-finite value.
-template <int D, int Q>
-__device__ __forceinline__ bool neumann_row(const GeomPtrs& gp, int32_t e, const double* ctr, const double* x0h,
-                                            double* m, double& w, double wpow) {
-  constexpr int M = Dims<D, Q>::M, M1 = Dims<D, Q>::M1;
-  double delta[3] = {0, 0, 0};
-  double d2 = 0;
-  for (int ax = 0; ax < D; ++ax) {
-    delta[ax] = ctr[ax] - x0h[ax];
-    d2 += delta[ax] * delta[ax];
-  }
-  w = row_weight(d2, wpow);
-  const double sc = w / gp.eb_mom[(long long)e * M];
-  static_for<0, M>([&](auto I) { m[I] = 0.0; });
-  static_for<0, D>([&](auto AX) {
-    double nu[M1];
-    const double* src = gp.eb_nmom + ((long long)e * D + AX) * M1;
-    static_for<0, M1>([&](auto I) { nu[I] = src[I]; });
-    recentre<D, Q - 1>(nu, delta);
-    static_for<0, M>([&](auto I) {
-      constexpr int pd = kMono<D, Q>.e[I][AX];
-      if constexpr (pd > 0) {
-        constexpr int j = mono_index<D>(kMono<D, Q>.e[I][0] - (AX == 0), kMono<D, Q>.e[I][1] - (AX == 1),
-                                        kMono<D, Q>.e[I][2] - (AX == 2));
-        m[I] = fma((double)pd, nu[j], m[I]);
-      }
-    });
-  });
-  bool finite = isfinite(sc);
-  static_for<0, M>([&](auto I) {
-    m[I] *= sc;
-    finite = finite && isfinite(m[I]);
-  });
-  return finite;
-}
-
-// Shared memory of one face (one wave).
-template <int D, int Q, int NPAD>
-struct FaceSmem {
-  static constexpr int M = Dims<D, Q>::M, MS = Dims<D, Q>::MS, M1 = Dims<D, Q>::M1;
-  double Bs[NPAD * MS];      // rows of B = W A~
-  double Ls[M * MS];         // Gram matrix, then the pivot rows of the inversion
-  double vec[2][M + 1];      // F~ and a broadcast vector
-  double ys[M + 1];          // y = G^-1 F~
-  double zs[NPAD];           // z = B y
-  double wls[NPAD];          // W
-  double nus[D][M1];         // EB normal moments about x0
-};
-
-// Everything about the face that the row and flux computations need.
-struct FaceInfo {
-  int32_t F;
-  int gi, kind, dn;
-  int32_t ref;
-  int64_t n_vol, n_eb, phi0, rp;
-  int N;
-  double x0h[3];             // x0 / h
-  double off[3];             // EB faces: centroid offset from the cut cell's centre (/h)
-  int32_t owner_cell;        // EB faces: the cut cell
-};
-
-// x0 of the face (in units of h): the face centre, or for an EB face the centroid of its
-// cut volume (whose offset from the cell centre is kept in fi.off).  Loads only.
-template <int D, int Q>
-__device__ __forceinline__ void face_x0(const GridDims& g, const GeomPtrs& gp, FaceInfo& fi) {
-  constexpr int M = Dims<D, Q>::M;
-  const int dn = fi.dn;
-  for (int ax = 0; ax < 3; ++ax) { fi.x0h[ax] = 0.0; fi.off[ax] = 0.0; }
-  fi.owner_cell = -1;
-  if (fi.kind == 0) {
-    const long long loc = fi.ref - g.foff[dn];
-    const int m0 = g.n[0] + (dn == 0), m1 = g.n[1] + (dn == 1);
-    const int j[3] = {(int)(loc % m0), (int)((loc / m0) % m1), (int)(loc / ((long long)m0 * m1))};
-    for (int ax = 0; ax < D; ++ax) fi.x0h[ax] = (ax == dn) ? (double)j[ax] : j[ax] + 0.5;
-    return;
-  }
-  const int32_t c = gp.eb_cell[fi.ref];
-  fi.owner_cell = c;
-  const int cown[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
-  const double* vm = gp.vol_mom + (long long)c * M;
-  const double k0 = vm[0];
-  for (int ax = 0; ax < D; ++ax) {
-    fi.off[ax] = vm[1 + ax] / k0;          // first moments: degree-1 monomials e_1..e_D
-    fi.x0h[ax] = cown[ax] + 0.5 + fi.off[ax];
-  }
-}
-
-// The flux vector F~ (in sm.vec[0]) and, for EB faces, the normal moments re-centred to x0
-// (sm.nus, lanes 0..D-1 one component each).
-template <int D, int Q, int NPAD>
-__device__ __forceinline__ void face_flux(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
-                                          FaceSmem<D, Q, NPAD>& sm, int lane) {
-  constexpr int M = Dims<D, Q>::M, Mf = Dims<D, Q>::Mf, M1 = Dims<D, Q>::M1;
-  const int dn = fi.dn;
-  if (fi.kind == 0) {
-    // F~_p = face moment of p - e_d when p_d = 1 (reference normal +e_d)
-    const double* fm = gp.face_mom[dn] + (fi.ref - g.foff[dn]) * Mf;
-    if (lane < M) {
-      double fv = 0.0;
-      constexpr auto& T = kMono<D, Q>;
-      const int e0 = T.e[lane][0], e1 = T.e[lane][1], e2 = T.e[lane][2];
-      const int pd = (dn == 0) ? e0 : (dn == 1 ? e1 : e2);
-      if (pd == 1) {
-        int s;
-        if (D == 2) s = mono_index<1>(dn == 0 ? e1 : e0, 0, 0);
-        else if (dn == 0) s = mono_index<2>(e1, e2, 0);
-        else if (dn == 1) s = mono_index<2>(e0, e2, 0);
-        else s = mono_index<2>(e0, e1, 0);
-        fv = fm[s];
-      }
-      sm.vec[0][lane] = fv;
-    }
-    __syncthreads();
-    return;
-  }
-  if (lane < D) {
-    double nu[M1];
-    const double* src = gp.eb_nmom + ((long long)fi.ref * D + lane) * M1;
-    static_for<0, M1>([&](auto I) { nu[I] = src[I]; });
-    double dl[3] = {-fi.off[0], -fi.off[1], -fi.off[2]};   // (c - x0)/h
-    recentre<D, Q - 1>(nu, dl);
-    static_for<0, M1>([&](auto I) { sm.nus[lane][I] = nu[I]; });
-  }
-  __syncthreads();
-  if (lane < M) {
-    constexpr auto& T = kMono<D, Q>;
-    double fv = 0.0;
-    for (int ax = 0; ax < D; ++ax) {
-      int e[3] = {T.e[lane][0], T.e[lane][1], T.e[lane][2]};
-      const int p = e[ax];
-      if (p > 0) {
-        e[ax] -= 1;
-        fv += p * sm.nus[ax][mono_index<D>(e[0], e[1], e[2])];
-      }
-    }
-    sm.vec[0][lane] = fv;
-  }
-  __syncthreads();
-}
-
-// Rows, Gram matrix, inverse and the refined semi-normal solve of one face.  Leaves B, W,
-// z and y in shared memory and -G^^-1 (row `lane`) in a[], the column
-// equilibration in sdiag.  Returns the face status.
-template <int D, int Q, int NPAD, bool NEU = false>
-__device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
-                                            const int32_t* __restrict__ vol_cell, const int32_t* __restrict__ box_lf,
-                                            const int32_t* __restrict__ col, FaceSmem<D, Q, NPAD>& sm, int lane,
-                                            double* a, double& sdiag, double wpow) {
-  using DM = Dims<D, Q>;
-  constexpr int M = DM::M, MT = DM::MT, MS = DM::MS;
-  double* Bs = sm.Bs;
-  double* Ls = sm.Ls;
-  const int N = fi.N;
-
-  // ---- rows of B ----------------------------------------------------------------------
-  // Lane r builds rows r, r + 64, ...: every row's index chain (col -> cell -> moments) is
-  // issued before the first row is finished, so the dependent loads of all rows overlap.
-  constexpr int NR = (NPAD + 63) / 64;
-  bool finite = true;
-  RowSource rsrc[NR];
-  static_for<0, NR>([&](auto R) {
-    const int r = lane + 64 * R;
-    if (r < N) rsrc[R] = row_source<D, Q>(g, gp, (int64_t)col[fi.rp + r] - fi.phi0, fi.n_vol, fi.n_eb, vol_cell,
-                                          box_lf);
-  });
-  static_for<0, NR>([&](auto R) {
-    const int r = lane + 64 * R;
-    if (r < NPAD) {
-      double m[M];
-      double wr = 0.0;
-      if (r < N) {
-        if constexpr (NEU) {
-          if (rsrc[R].eb >= 0) {
-            finite = neumann_row<D, Q>(gp, rsrc[R].eb, rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
-          } else {
-            load_row_moments<D, Q>(rsrc[R], m);
-            finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
-          }
-        } else {
-          load_row_moments<D, Q>(rsrc[R], m);
-          finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
-        }
-      } else {
-        static_for<0, M>([&](auto I) { m[I] = 0.0; });
-      }
-      static_for<0, M>([&](auto I) { Bs[r * MS + I] = m[I]; });
-      sm.wls[r] = wr;
-      sm.zs[r] = 0.0;
-    }
-  });
-  face_flux<D, Q, NPAD>(g, gp, fi, sm, lane);
-  const bool allfinite = __all(finite) && __all(lane >= M || isfinite(sm.vec[0][lane < M ? lane : 0]));
-
-  // ---- G = B^T B: full 16-column tiles on the matrix cores --------------------------------
-  // (v_mfma_f64_16x16x4f64, upper triangle of tiles, rows of B as the contraction index).
-  // A narrow trailing block (at most 4 columns, e.g. 3 of M = 35) is done on the vector
-  // ALUs instead: as a 16-wide tile it would be mostly padding, and FP64 MFMA has no more
-  // throughput than FP64 FMA on this chip.
-  constexpr int MTF = (MT > 1 && M - 16 * (MT - 1) <= 4) ? MT - 1 : MT;
-  constexpr int MV = M - 16 * MTF;
-  dbl4 acc[MTF][MTF];
-#pragma unroll
-  for (int i = 0; i < MTF; ++i)
-#pragma unroll
-    for (int j = 0; j < MTF; ++j) acc[i][j] = dbl4{0, 0, 0, 0};
-  const int lr = lane >> 4, lc = lane & 15;
-#pragma unroll
-  for (int k0 = 0; k0 < NPAD; k0 += 4) {
-    double x[MTF];
-#pragma unroll
-    for (int i = 0; i < MTF; ++i) {
-      const int cidx = 16 * i + lc;
-      x[i] = (cidx < M) ? Bs[(k0 + lr) * MS + cidx] : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < MTF; ++i)
-#pragma unroll
-      for (int j = i; j < MTF; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[i], x[j], acc[i][j], 0, 0, 0);
-  }
-  // tile (i, j), register q holds G[16i + lane/16 + 4q][16j + lane%16] (the output layout
-  // of v_mfma_f64_16x16x4f64); each entry of the symmetric matrix is written once
-  // (r <= c) together with its mirror
-#pragma unroll
-  for (int i = 0; i < MTF; ++i)
-#pragma unroll
-    for (int j = i; j < MTF; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * i + lr + 4 * q, c = 16 * j + lc;
-        if (r < M && c < M && r <= c) {
-          Ls[r * MS + c] = acc[i][j][q];
-          Ls[c * MS + r] = acc[i][j][q];
-        }
-      }
-  if constexpr (MV > 0) {
-    // lane l: G[l][16 MTF + c] for the trailing columns c (and the mirrored entries)
-    if (lane < M) {
-      double g0[MV], g1[MV];
-      static_for<0, MV>([&](auto C) { g0[C] = 0.0; g1[C] = 0.0; });
-      for (int k = 0; k < NPAD; k += 2) {
-        const double b0 = Bs[k * MS + lane], b1 = Bs[(k + 1) * MS + lane];
-        static_for<0, MV>([&](auto C) {
-          g0[C] = fma(b0, Bs[k * MS + 16 * MTF + C], g0[C]);
-          g1[C] = fma(b1, Bs[(k + 1) * MS + 16 * MTF + C], g1[C]);
-        });
-      }
-      static_for<0, MV>([&](auto C) {
-        const double v = g0[C] + g1[C];
-        Ls[lane * MS + 16 * MTF + C] = v;
-        Ls[(16 * MTF + C) * MS + lane] = v;
-      });
-    }
-  }
-  __syncthreads();
-
-  // ---- equilibrate to unit diagonal and invert: lane i holds row i ----------------------------
-  // Symmetric Gauss-Jordan sweeps over the pivots k = 0..M-1 turn G^ into -G^-1 in place;
-  // the pivot of step k is the k-th Schur complement pivot (L_kk^2 of the Cholesky factor),
-  // which gives the rank test.  Lane k's row is the pivot row (= column, by symmetry); the
-  // other lanes read it with v_readlane, so a sweep step touches neither LDS nor a barrier.
-  const bool act = lane < M;
-  const int li = act ? lane : 0;         // clamped index for inactive lanes' LDS reads
-  sdiag = act ? 1.0 / sqrt(Ls[li * MS + li]) : 1.0;
-  static_for<0, M>([&](auto J) { a[J] = act ? Ls[li * MS + J] * sdiag * readlane_f64(sdiag, J) : 0.0; });
-  double pmax = 0.0, pmin = 1e300;
-  // Step k:  a_ij -= (a_ik / d) a_kj  (i, j != k);  a_ik /= d;  a_kj /= d;  a_kk = -1/d.
-  // Each lane scales its multiplier once (u = a_ik / d; on lane k, 1 - 1/d turns the
-  // pivot row into a_kj / d), so every entry is one FMA fed straight by v_readlane.  The
-  // pivot row is read eight entries at a time before their FMAs: read one by one, each
-  // read waits for the previous FMA to release its scalar registers (measured 12 % slower).
-  static_for<0, M>([&](auto K) {
-    constexpr int k = K;
-    const double d = readlane_f64(a[k], k);
-    const double sq = sqrt(d > 0.0 ? d : 0.0);
-    pmax = fmax(pmax, sq);
-    pmin = fmin(pmin, sq);
-    const double rd = recip_f64(d);
-    const double u = (lane == k) ? 1.0 - rd : a[k] * rd;
-    static_for<0, (M + 7) / 8>([&](auto G) {
-      double pr[8];
-      static_for<0, 8>([&](auto I) {
-        constexpr int j = 8 * G + I;
-        if constexpr (j < M && j != k) pr[I] = readlane_f64(a[j], k);
-      });
-      static_for<0, 8>([&](auto I) {
-        constexpr int j = 8 * G + I;
-        if constexpr (j < M && j != k) a[j] = fma(-u, pr[I], a[j]);
-      });
-    });
-    a[k] = (lane == k) ? -rd : u;
-  });
-  const bool rankok = (pmin > kRankTol * pmax) && (pmax > 0.0);
-  int st = CUTCELL_STATUS_OK;
-  if (!allfinite) st = CUTCELL_STATUS_NONFINITE;
-  else if (!rankok) st = CUTCELL_STATUS_RANK_DEFICIENT;
-
-  // ---- semi-normal solve with refinement ----------------------------------------------------
-  // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs).  Lane p holds
-  // component p of F~, rhs and y; lane r holds z of its rows r, r + 64.
-  const double fv = act ? sm.vec[0][lane] : 0.0;
-  double rhs = fv * sdiag;
-  double ysum = 0.0;
-  double zr[NR];
-  static_for<0, NR>([&](auto R) { zr[R] = 0.0; });
-  for (int it = 0; it <= kRefine; ++it) {
-    double tq[4] = {0.0, 0.0, 0.0, 0.0};
-    static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], readlane_f64(rhs, J), tq[J % 4]); });
-    const double t = (tq[0] + tq[1]) + (tq[2] + tq[3]);
-    const double dy = act ? t * sdiag : 0.0;
-    ysum += dy;
-    // z += B dy
-    static_for<0, NR>([&](auto R) {
-      const int r = lane + 64 * R;
-      if (r < NPAD) {
-        double sq4[4] = {0.0, 0.0, 0.0, 0.0};
-        static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], readlane_f64(dy, J), sq4[J % 4]); });
-        zr[R] += (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
-      }
-    });
-    if (it == kRefine) break;
-    // residual of B^T z = F~, equilibrated; z goes through LDS, B^T is read by columns
-    static_for<0, NR>([&](auto R) {
-      const int r = lane + 64 * R;
-      if (r < NPAD) sm.zs[r] = zr[R];
-    });
-    __syncthreads();
-    double res = 0.0;
-    if (act) {
-      double r0 = fv, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-#pragma unroll 4
-      for (int r = 0; r < NPAD; r += 4) {
-        r0 = fma(-Bs[(r + 0) * MS + lane], sm.zs[r + 0], r0);
-        r1 = fma(-Bs[(r + 1) * MS + lane], sm.zs[r + 1], r1);
-        r2 = fma(-Bs[(r + 2) * MS + lane], sm.zs[r + 2], r2);
-        r3 = fma(-Bs[(r + 3) * MS + lane], sm.zs[r + 3], r3);
-      }
-      res = (r0 + r1) + (r2 + r3);
-    }
-    rhs = res * sdiag;
-    __syncthreads();
-  }
-  static_for<0, NR>([&](auto R) {
-    const int r = lane + 64 * R;
-    if (r < NPAD) sm.zs[r] = zr[R];
-  });
-  if (act) sm.ys[lane] = ysum;
-  __syncthreads();
-  return st;
-}
-
-struct StencilArgs {
-  GridDims g;
-  int G;
-  double hscale;
-  const int32_t* perm;
-  long long nbin;
-  const int32_t* fcode;
-  const int32_t* fref;
-  const GeomPtrs* geoms;
-  const int64_t* counts;
-  const int64_t* offs;
-  const int32_t* vol_cell_ws;
-  const int32_t* box_lf_ws;
-  const int64_t* row_ptr;
-  const int32_t* col;
-  // schedule: workgroup b runs on XCD b % xcd (the dispatcher deals workgroups out to the
-  // XCDs in turn) and walks that XCD's contiguous chunk of the bin with stride per_xcd
-  int xcd;
-  int per_xcd;
-  double h;            // grid spacing (Neumann rows carry one more power of h)
-  double wpow;         // weight exponent p of W = (2 |delta|)^-p
-};
-
-// Faces of a bin taken by workgroup blockIdx.x in turn (-1 when done).  With xcd = 1 and a
-// grid of nbin workgroups this is one face per workgroup in bin order.
-struct FaceWalk {
-  long long chunk, k, base;
-  int step;
-  __device__ FaceWalk(const StencilArgs& A) {
-    const int b = blockIdx.x;
-    chunk = (A.nbin + A.xcd - 1) / A.xcd;
-    base = (long long)(b % A.xcd) * chunk;
-    k = b / A.xcd;
-    step = A.per_xcd;
-  }
-  __device__ long long next() {
-    if (k >= chunk) return -1;
-    const long long t = base + k;
-    k += step;
-    return t;
-  }
-};
-
-__device__ __forceinline__ FaceInfo face_info(const StencilArgs& A, long long t) {
-  FaceInfo fi;
-  fi.F = A.perm[t];
-  const int32_t code = A.fcode[fi.F];
-  fi.gi = code >> 4;
-  fi.kind = (code >> 2) & 3;
-  fi.dn = code & 3;
-  fi.ref = A.fref[fi.F];
-  fi.n_vol = A.counts[4 * fi.gi + 0];
-  fi.n_eb = A.counts[4 * fi.gi + 1];
-  fi.phi0 = A.offs[fi.gi];
-  fi.rp = A.row_ptr[fi.F];
-  fi.N = (int)(A.row_ptr[fi.F + 1] - fi.rp);
-  return fi;
-}
-
-// One face per workgroup (WALK = false: face t of the bin, t from the XCD mapping), or a
-// persistent workgroup that walks its chunk (WALK = true).  Two instances because the
-// loop costs the single-face kernel registers.
-template <int D, int Q, int NPAD, bool NEU>
-__device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, FaceSmem<D, Q, NPAD>& sm, int lane,
-                                             double* __restrict__ val, int8_t* __restrict__ status, int32_t* flagged) {
-  constexpr int M = Dims<D, Q>::M;
-  FaceInfo fi = face_info(A, t);
-  const GeomPtrs gp = A.geoms[fi.gi];
-  face_x0<D, Q>(A.g, gp, fi);
-  double a[M];
-  double sdiag;
-  const int st = face_forward<D, Q, NPAD, NEU>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
-                                               A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a,
-                                               sdiag, A.wpow);
-  for (int r = lane; r < fi.N; r += 64) {
-    double v = (st == CUTCELL_STATUS_OK) ? A.hscale * sm.wls[r] * sm.zs[r] : 0.0;
-    if constexpr (NEU) {
-      const int64_t k = (int64_t)A.col[fi.rp + r] - fi.phi0;
-      if (k >= fi.n_vol && k < fi.n_vol + fi.n_eb) v *= A.h;
-    }
-    val[fi.rp + r] = v;
-  }
-  if (lane == 0) {
-    status[fi.F] = (int8_t)st;
-    if (st != CUTCELL_STATUS_OK) atomicAdd(flagged, 1);
-  }
-}
-
-template <int D, int Q, int NPAD, bool WALK, bool NEU = false>
-__global__ __launch_bounds__(64) void k_stencil(StencilArgs A, double* __restrict__ val, int8_t* __restrict__ status,
-                                               int32_t* flagged) {
-  __shared__ FaceSmem<D, Q, NPAD> sm;
-  const int lane = threadIdx.x;
-  FaceWalk walk(A);
-  if constexpr (!WALK) {
-    const long long t = walk.next();
-    if (t >= 0 && t < A.nbin) stencil_face<D, Q, NPAD, NEU>(A, t, sm, lane, val, status, flagged);
-  } else {
-    for (long long t = walk.next(); t >= 0 && t < A.nbin; t = walk.next()) {
-      stencil_face<D, Q, NPAD, NEU>(A, t, sm, lane, val, status, flagged);
-      __syncthreads();   // the next face reuses the shared memory
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// Adjoint of the stencil of one face (the derivative of the solution of Sec. 2.2.1).
-// With s~ = W z, z = B y, y = G^-1 F~, G = B^T B and a given s~bar:
-//   zbar = W s~bar,  Wbar_i = s~bar_i z_i (through s~ = W z),
-//   w = G^-1 B^T zbar (a least-squares solve, refined like the forward), r = zbar - B w,
-//   Bbar = r y^T - z w^T,  Fbar = w,  Abar = W Bbar,  Wbar_i += Bbar_i . A~_i.
-// Bbar_i . B_i = r_i z_i - z_i (B w)_i needs no pass over the row.  The rows' moments
-// get S(delta_i)^T Abar_i / mu0 - e_0 (Abar_i . A~_i) / mu0; that sum over the faces a
-// row appears in is formed per Phi entry by k_moment_reduce from what this kernel keeps:
-// y and w of the face, x0, and (W r, W z) per row.  For an EB face x0 is the centroid of
-// the cut volume, so every row's delta and weight and the re-centred normal moments also
-// depend on that volume's moments 0..D; their gradient goes to owner_grad.
-
-template <int D, int Q, int NPAD>
-__global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, BackwardArgs B) {
-  using DM = Dims<D, Q>;
-  constexpr int M = DM::M, MS = DM::MS, Mf = DM::Mf, M1 = DM::M1;
-  __shared__ FaceSmem<D, Q, NPAD> sm;
-  __shared__ double zbar[NPAD];   // W s~bar, then the residual r = zbar - B w
-  __shared__ double bw[NPAD];     // B w
-  __shared__ double wv[M + 1];    // w
-  __shared__ double gdx[64][3];   // per-lane sums of dl/dx0 over the rows
-  const long long t = blockIdx.x;
-  if (t >= A.nbin) return;
-  const int lane = threadIdx.x;
-  FaceInfo fi = face_info(A, t);
-  const GeomPtrs gp = A.geoms[fi.gi];
-  face_x0<D, Q>(A.g, gp, fi);
-  double a[M];
-  double sdiag;
-  const int32_t* vol_cell = A.vol_cell_ws + (long long)fi.gi * A.g.ncell;
-  const int32_t* box_lf = A.box_lf_ws + (long long)fi.gi * A.g.nboxslot;
-  const bool act = lane < M;
-  const int N = fi.N;
-  double* yw = B.face_yw + (long long)fi.F * 2 * M;
-  double* og = B.owner_grad + (long long)fi.F * 4;
-  if (lane < 4) B.face_x0[(long long)fi.F * 4 + lane] = (lane < 3) ? fi.x0h[lane] : 0.0;
-  // a face whose stencil gets no cotangent contributes nothing: skip its solve
-  bool any = false;
-  for (int r = lane; r < N; r += 64) any = any || (B.val_bar[fi.rp + r] != 0.0);
-  if (!__any(any)) {
-    for (int r = lane; r < N; r += 64) {
-      B.nz_rz[2 * (fi.rp + r)] = 0.0;
-      B.nz_rz[2 * (fi.rp + r) + 1] = 0.0;
-      if (B.weight_bar) B.weight_bar[fi.rp + r] = 0.0;
-    }
-    if (act) { yw[lane] = 0.0; yw[M + lane] = 0.0; }
-    if (lane < 4) og[lane] = 0.0;
-    return;
-  }
-  const int st = face_forward<D, Q, NPAD>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag, A.wpow);
-  const double* Bs = sm.Bs;
-  if (st != CUTCELL_STATUS_OK) {   // a flagged face has s = 0 whatever its inputs: no gradient
-    for (int r = lane; r < N; r += 64) {
-      B.nz_rz[2 * (fi.rp + r)] = 0.0;
-      B.nz_rz[2 * (fi.rp + r) + 1] = 0.0;
-      if (B.weight_bar) B.weight_bar[fi.rp + r] = 0.0;
-    }
-    if (act) { yw[lane] = 0.0; yw[M + lane] = 0.0; }
-    if (lane < 4) og[lane] = 0.0;
-    return;
-  }
-  // s~bar = h^(D-2) val_bar;  zbar = W s~bar;  the direct part of Wbar in gdx-free regs
-  for (int r = lane; r < NPAD; r += 64) {
-    const double sb = (r < N) ? A.hscale * B.val_bar[fi.rp + r] : 0.0;
-    zbar[r] = sm.wls[r] * sb;
-  }
-  __syncthreads();
-  // w = G^-1 B^T zbar, refined:  w += G^-1 B^T (zbar - B w); lane p holds w_p
-  constexpr int NR = (NPAD + 63) / 64;
-  double wl = 0.0;
-  for (int it = 0; it <= kRefine; ++it) {
-    double res = 0.0;
-    if (act) {
-      double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
-      for (int r = 0; r < NPAD; r += 4) {
-        double e0 = zbar[r + 0], e1 = zbar[r + 1], e2 = zbar[r + 2], e3 = zbar[r + 3];
-        if (it > 0) { e0 -= bw[r + 0]; e1 -= bw[r + 1]; e2 -= bw[r + 2]; e3 -= bw[r + 3]; }
-        r0 = fma(Bs[(r + 0) * MS + lane], e0, r0);
-        r1 = fma(Bs[(r + 1) * MS + lane], e1, r1);
-        r2 = fma(Bs[(r + 2) * MS + lane], e2, r2);
-        r3 = fma(Bs[(r + 3) * MS + lane], e3, r3);
-      }
-      res = (r0 + r1) + (r2 + r3);
-    }
-    const double rhs = res * sdiag;
-    double tq[4] = {0.0, 0.0, 0.0, 0.0};
-    static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], readlane_f64(rhs, J), tq[J % 4]); });
-    if (act) wl += ((tq[0] + tq[1]) + (tq[2] + tq[3])) * sdiag;
-    __syncthreads();
-    static_for<0, NR>([&](auto R) {
-      const int r = lane + 64 * R;
-      if (r < NPAD) {
-        double s = 0.0;
-        static_for<0, M>([&](auto J) { s = fma(Bs[r * MS + J], readlane_f64(wl, J), s); });
-        bw[r] = s;
-      }
-    });
-    __syncthreads();
-  }
-  if (act) wv[lane] = wl;
-  __syncthreads();
-  if (act) {
-    yw[lane] = sm.ys[lane];
-    yw[M + lane] = wl;
-  }
-  // per row: r = zbar - B w;  Wbar;  (W r, W z) for the moment reduction;  EB x0 terms
-  double gx[3] = {0, 0, 0};
-  for (int r = lane; r < N; r += 64) {
-    const double W = sm.wls[r], zz = sm.zs[r];
-    const double rr = zbar[r] - bw[r];
-    const double sb = A.hscale * B.val_bar[fi.rp + r];
-    const double bdot = zz * (rr - bw[r]);            // Bbar_i . B_i
-    const double wtot = sb * zz + bdot / W;           // dl/dW_i
-    if (B.weight_bar) B.weight_bar[fi.rp + r] = wtot;
-    B.nz_rz[2 * (fi.rp + r)] = W * rr;
-    B.nz_rz[2 * (fi.rp + r) + 1] = W * zz;
-    if (fi.kind == 1) {
-      // delta_i = x_i/h - x0h: d B_ip / d delta_d = p_d B_i,p-e_d (weight fixed), and
-      // dW/d delta_d = -p W delta_d / |delta|^2 outside half a cell (W = (2|delta|)^-p)
-      const RowSource rs = row_source<D, Q>(A.g, gp, (int64_t)A.col[fi.rp + r] - fi.phi0, fi.n_vol, fi.n_eb,
-                                            vol_cell, box_lf);
-      double dl[3] = {0, 0, 0}, d2 = 0.0;
-      for (int ax = 0; ax < D; ++ax) {
-        dl[ax] = rs.ctr[ax] - fi.x0h[ax];
-        d2 += dl[ax] * dl[ax];
-      }
-      double gd[3] = {0, 0, 0};
-      static_for<0, M>([&](auto P) {
-        constexpr int p = P;
-        const double bb = rr * sm.ys[p] - zz * wv[p];   // Bbar_ip
-        static_for<0, D>([&](auto AX) {
-          constexpr int ax = AX;
-          constexpr int pd = kMono<D, Q>.e[p][ax];
-          if constexpr (pd > 0) {
-            constexpr int q = mono_index<D>(kMono<D, Q>.e[p][0] - (ax == 0), kMono<D, Q>.e[p][1] - (ax == 1),
-                                            kMono<D, Q>.e[p][2] - (ax == 2));
-            gd[ax] = fma(bb * pd, Bs[r * MS + q], gd[ax]);
-          }
-        });
-      });
-      if (sqrt(d2) >= 0.5)
-        for (int ax = 0; ax < D; ++ax) gd[ax] += wtot * (-A.wpow * W * dl[ax] / d2);
-      for (int ax = 0; ax < D; ++ax) gx[ax] -= gd[ax];   // d delta / d x0h = -1
-    }
-  }
-  // flux-vector gradient Fbar = w
-  if (fi.kind == 0) {
-    if (lane < 4) og[lane] = 0.0;
-    if (act) {
-      constexpr auto& T = kMono<D, Q>;
-      const int dn = fi.dn;
-      const int e0 = T.e[lane][0], e1 = T.e[lane][1], e2 = T.e[lane][2];
-      const int pd = (dn == 0) ? e0 : (dn == 1 ? e1 : e2);
-      if (pd == 1) {
-        int s;
-        if (D == 2) s = mono_index<1>(dn == 0 ? e1 : e0, 0, 0);
-        else if (dn == 0) s = mono_index<2>(e1, e2, 0);
-        else if (dn == 1) s = mono_index<2>(e0, e2, 0);
-        else s = mono_index<2>(e0, e1, 0);
-        B.grads[fi.gi].face_mom[dn][(fi.ref - A.g.foff[dn]) * Mf + s] = wv[lane];
-      }
-    }
-    return;
-  }
-  // EB face: F~_p = sum_d p_d nu'_{d, p - e_d} with nu' the normal moments re-centred by
-  // delta0 = (c - x0)/h:  nu'bar_{d,q} = (q_d + 1) w_{q + e_d},  nubar = S(delta0)^T nu'bar,
-  // and d nu'_{d,q} / d delta0_k = q_k nu'_{d, q - e_k}
-  for (int ax = 0; ax < 3; ++ax) gdx[lane][ax] = gx[ax];
-  __syncthreads();
-  if (lane < D) {
-    double nb[M1];
-    double g0[3] = {0, 0, 0};
-    static_for<0, M1>([&](auto I) {
-      constexpr int i = I;
-      constexpr int q0 = kMono<D, Q - 1>.e[i][0], q1 = kMono<D, Q - 1>.e[i][1], q2 = kMono<D, Q - 1>.e[i][2];
-      const int qd = (lane == 0) ? q0 : (lane == 1 ? q1 : q2);
-      const int up = mono_index<D>(q0 + (lane == 0), q1 + (lane == 1), q2 + (lane == 2));
-      nb[i] = (qd + 1) * wv[up];
-    });
-    static_for<0, M1>([&](auto I) {
-      constexpr int i = I;
-      static_for<0, D>([&](auto K) {
-        constexpr int k = K;
-        constexpr int qk = kMono<D, Q - 1>.e[i][k];
-        if constexpr (qk > 0) {
-          constexpr int src = mono_index<D>(kMono<D, Q - 1>.e[i][0] - (k == 0), kMono<D, Q - 1>.e[i][1] - (k == 1),
-                                            kMono<D, Q - 1>.e[i][2] - (k == 2));
-          g0[k] = fma(nb[i] * qk, sm.nus[lane][src], g0[k]);
-        }
-      });
-    });
-    double d0[3] = {-fi.off[0], -fi.off[1], -fi.off[2]};
-    recentre_T<D, Q - 1>(nb, d0);
-    double* dst = B.grads[fi.gi].eb_nmom + ((long long)fi.ref * D + lane) * M1;
-    static_for<0, M1>([&](auto I) { dst[I] = nb[I]; });
-    for (int k = 0; k < 3; ++k) sm.vec[1][lane * 3 + k] = g0[k];   // dl/d delta0 from component `lane`
-  }
-  __syncthreads();
-  if (lane == 0) {
-    // dl/dx0h = sum over rows (gdx) - dl/d delta0;  x0h_d = centre_d + m^{e_d} / m^0
-    double gxh[3] = {0, 0, 0};
-    for (int l = 0; l < 64; ++l)
-      for (int ax = 0; ax < D; ++ax) gxh[ax] += gdx[l][ax];
-    for (int c = 0; c < D; ++c)
-      for (int k = 0; k < D; ++k) gxh[k] -= sm.vec[1][c * 3 + k];
-    const double* vm = gp.vol_mom + (long long)fi.owner_cell * M;
-    const double m0 = vm[0];
-    double g0 = 0.0;
-    for (int ax = 0; ax < D; ++ax) {
-      og[1 + ax] = gxh[ax] / m0;
-      g0 -= gxh[ax] * vm[1 + ax] / (m0 * m0);
-    }
-    og[0] = g0;
-    for (int ax = D; ax < 3; ++ax) og[1 + ax] = 0.0;
-  }
-}
 
 // Faces with fewer rows than monomials: zero stencil, status INSUFFICIENT_ROWS -- except,
 // under Neumann EB conditions, the EB faces, whose one-row stencil is their area
@@ -787,30 +49,6 @@ __global__ __launch_bounds__(64) void k_copy_template(const int32_t* __restrict_
   }
 }
 
-static StencilArgs stencil_args(const Work& w, double hscale, const int32_t* perm, long long nbin,
-                                const int64_t* row_ptr, const int32_t* col) {
-  StencilArgs A;
-  A.xcd = 1;
-  A.per_xcd = 1;
-  A.g = w.dims;
-  A.G = w.G;
-  A.hscale = hscale;
-  A.perm = perm;
-  A.nbin = nbin;
-  A.fcode = w.fcode;
-  A.fref = w.fref;
-  A.geoms = w.geoms;
-  A.counts = w.counts;
-  A.offs = w.offs;
-  A.vol_cell_ws = w.vol_cell;
-  A.box_lf_ws = w.box_lf;
-  A.row_ptr = row_ptr;
-  A.col = col;
-  A.h = 0.0;
-  A.wpow = 5.0;
-  return A;
-}
-
 // faces with fewer rows than monomials carry no gradient
 __global__ void k_insufficient_backward(const int32_t* __restrict__ perm, long long n,
                                         const int64_t* __restrict__ row_ptr, int M, BackwardArgs B) {
@@ -829,96 +67,40 @@ __global__ void k_insufficient_backward(const int32_t* __restrict__ perm, long l
   }
 }
 
-// Launch shape of one bin: xcd = 1 or the number of XCDs whose chunks the bin is split
-// into; per_xcd = 0 for one workgroup per face, else the persistent workgroups per chunk.
-struct BinSchedule {
-  int xcd = 1;
-  int per_xcd = 0;
-};
-
-template <int D, int Q, int NPAD>
-static void launch_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, const int64_t* row_ptr,
-                       const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
-                       BinSchedule sc, bool neu, double h, double wpow) {
-  if (nbin <= 0) return;
-  StencilArgs A = stencil_args(w, hscale, perm, nbin, row_ptr, col);
-  A.wpow = wpow;
-  if (bw) {
-    hipLaunchKernelGGL((k_stencil_backward<D, Q, NPAD>), dim3((unsigned)nbin), dim3(64), 0, st, A, *bw);
-    return;
-  }
-  const int X = sc.xcd > 1 ? sc.xcd : 1;
-  const long long chunk = (nbin + X - 1) / X;
-  const long long per = sc.per_xcd > 0 ? std::min<long long>(sc.per_xcd, chunk) : chunk;
-  A.xcd = X;
-  A.per_xcd = (int)per;
-  if (neu) {   // one workgroup per face (no persistent instance of the Neumann kernel)
-    A.per_xcd = (int)chunk;
-    A.h = h;
-    hipLaunchKernelGGL((k_stencil<D, Q, NPAD, false, true>), dim3((unsigned)(X * chunk)), dim3(64), 0, st, A, val,
-                       status, w.flagged);
-    return;
-  }
-  if (per < chunk)
-    hipLaunchKernelGGL((k_stencil<D, Q, NPAD, true>), dim3((unsigned)(X * per)), dim3(64), 0, st, A, val, status,
-                       w.flagged);
-  else
-    hipLaunchKernelGGL((k_stencil<D, Q, NPAD, false>), dim3((unsigned)(X * per)), dim3(64), 0, st, A, val, status,
-                       w.flagged);
-}
-
-template <int D, int Q>
-static int dispatch_bins(const Work& w, double hscale, const int32_t* bin_count, const int64_t* row_ptr,
-                         const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
-                         const BinSchedule* sched, int only_bin, bool neu, double h, double wpow) {
-  constexpr int M = binom(Q + D, D);
-  long long start = 0;
-  for (int b = 0; b < kMaxBins; ++b) {
-    const long long nb = bin_count[b];
-    const int32_t* p = w.perm + start;
-    start += nb;
-    if (nb == 0 || (only_bin >= 0 && b != only_bin)) continue;
-    const int npad = kBinRows * (b + 1);
-    if (npad < M) return fail(CUTCELL_E_INVALID_ARG, "internal: face with N >= M in a bin narrower than M");
-    switch (npad) {
-      case 16: if constexpr (M <= 16) launch_bin<D, Q, 16>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 32: if constexpr (M <= 32) launch_bin<D, Q, 32>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 48: launch_bin<D, Q, 48>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 64: launch_bin<D, Q, 64>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 80: launch_bin<D, Q, 80>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 96: launch_bin<D, Q, 96>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 112: launch_bin<D, Q, 112>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-      case 128: launch_bin<D, Q, 128>(w, hscale, p, nb, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); break;
-    }
-  }
-  const long long ninsuf = (only_bin < 0) ? bin_count[kMaxBins] : 0;
-  const long long ncopy = (only_bin < 0 && !bw) ? bin_count[kMaxBins + 1] : 0;
-  if (ncopy > 0)   // after the bins: the templates are solved by then (same stream)
-    hipLaunchKernelGGL(k_copy_template, dim3((unsigned)ncopy), dim3(64), 0, st, w.perm + start + bin_count[kMaxBins],
-                       ncopy, w.tmpl, row_ptr, val, status, w.flagged);
-  if (ninsuf > 0 && bw)
-    hipLaunchKernelGGL(k_insufficient_backward, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st,
-                       w.perm + start, ninsuf, row_ptr, (int)M, *bw);
-  else if (ninsuf > 0)
-    hipLaunchKernelGGL(k_insufficient, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st, w.perm + start,
-                       ninsuf, row_ptr, val, status, w.flagged, w.fcode, w.fref, w.geoms, (int)neu,
-                       D == 3 ? h * h : h, (int)M);
-  CC_HIP(hipGetLastError());
-  return CUTCELL_OK;
-}
-
 static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
                     const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
                     const BinSchedule* sched, int only_bin = -1) {
   double hscale = 1.0;
   for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
+  const bool neu = o.eb_bc == CUTCELL_BC_NEUMANN;
+  int rc = CUTCELL_E_UNSUPPORTED;
 #define CC_RB(DD, QQ) \
   if (o.dim == DD && o.order == QQ) \
-    return dispatch_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin, \
-                                 o.eb_bc == CUTCELL_BC_NEUMANN, o.h, o.weight_custom ? o.weight_power : 5.0);
+    rc = dispatch_row_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin, neu, o.h, \
+                                   o.weight_custom ? o.weight_power : 5.0);
   CC_RB(2, 2) CC_RB(2, 4) CC_RB(3, 2) CC_RB(3, 4)
 #undef CC_RB
-  return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");
+  if (rc == CUTCELL_E_UNSUPPORTED) return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");
+  if (rc != CUTCELL_OK) return rc;
+  // after the bins: faces with fewer rows than monomials, and the template copies (the
+  // templates are solved by then: same stream)
+  const int M = binom(o.order + o.dim, o.dim);
+  long long start = 0;
+  for (int b = 0; b < kMaxBins; ++b) start += bin_count[b];
+  const long long ninsuf = (only_bin < 0) ? bin_count[kMaxBins] : 0;
+  const long long ncopy = (only_bin < 0 && !bw) ? bin_count[kMaxBins + 1] : 0;
+  if (ncopy > 0)
+    hipLaunchKernelGGL(k_copy_template, dim3((unsigned)ncopy), dim3(64), 0, st, w.perm + start + bin_count[kMaxBins],
+                       ncopy, w.tmpl, row_ptr, val, status, w.flagged);
+  if (ninsuf > 0 && bw)
+    hipLaunchKernelGGL(k_insufficient_backward, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st,
+                       w.perm + start, ninsuf, row_ptr, M, *bw);
+  else if (ninsuf > 0)
+    hipLaunchKernelGGL(k_insufficient, dim3((unsigned)((ninsuf + 255) / 256)), dim3(256), 0, st, w.perm + start,
+                       ninsuf, row_ptr, val, status, w.flagged, w.fcode, w.fref, w.geoms, (int)neu,
+                       o.dim == 3 ? o.h * o.h : o.h, M);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
 }
 
 static void schedules_from(const cutcell_tuning* t, BinSchedule* sc) {

@@ -1,0 +1,7 @@
+// Stencil kernels of dimension 3, order 4 (one translation unit per (dimension, order),
+// so that they compile in parallel).
+#include "stencil_impl.hpp"
+
+namespace cutcell {
+CC_DISPATCH(3, 4, )
+}  // namespace cutcell
