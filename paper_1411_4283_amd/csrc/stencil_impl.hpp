@@ -888,9 +888,9 @@ constexpr bool split_bin() {
 }
 
 template <int D, int Q, int NPAD>
-static void launch_row_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, long long nlo,
-                           const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st,
-                           const BackwardArgs* bw, BinSchedule sc, bool neu, double h, double wpow) {
+void launch_row_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, long long nlo,
+                    const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st,
+                    const BackwardArgs* bw, BinSchedule sc, bool neu, double h, double wpow) {
   if constexpr (split_bin<D, Q, NPAD>()) {
     if (!bw && nlo > 0) {
       launch_bin<D, Q, NPAD - kBinRows / 2, true>(w, hscale, perm, nlo, row_ptr, col, val, status, st, bw, sc, neu, h,
@@ -902,9 +902,20 @@ static void launch_row_bin(const Work& w, double hscale, const int32_t* perm, lo
   launch_bin<D, Q, NPAD>(w, hscale, perm, nbin, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
 }
 
-// The row bins of one (dimension, order): one launch per bin (two for a split bin).  Each
-// (dimension, order) is instantiated in a file of its own (stencil_d*q*.hip), so the
-// library's kernels compile in parallel.
+// Explicit instantiations: each (dimension, order, bin) lives in one stencil_d*q*.hip file,
+// so the library's kernels compile in parallel (the 3D order-4 bins over three files).
+#define CC_ROW_BIN(DD, QQ, P, EXT) \
+  EXT template void launch_row_bin<DD, QQ, P>(const Work&, double, const int32_t*, long long, long long, \
+                                              const int64_t*, const int32_t*, double*, int8_t*, hipStream_t, \
+                                              const BackwardArgs*, BinSchedule, bool, double, double);
+#define CC_ROW_BINS_ALL(DD, QQ, EXT) \
+  CC_ROW_BIN(DD, QQ, 16, EXT) CC_ROW_BIN(DD, QQ, 32, EXT) CC_ROW_BIN(DD, QQ, 48, EXT) CC_ROW_BIN(DD, QQ, 64, EXT) \
+  CC_ROW_BIN(DD, QQ, 80, EXT) CC_ROW_BIN(DD, QQ, 96, EXT) CC_ROW_BIN(DD, QQ, 112, EXT) CC_ROW_BIN(DD, QQ, 128, EXT)
+CC_ROW_BINS_ALL(2, 2, extern) CC_ROW_BINS_ALL(2, 4, extern) CC_ROW_BINS_ALL(3, 2, extern)
+CC_ROW_BIN(3, 4, 48, extern) CC_ROW_BIN(3, 4, 64, extern) CC_ROW_BIN(3, 4, 80, extern)
+CC_ROW_BIN(3, 4, 96, extern) CC_ROW_BIN(3, 4, 112, extern) CC_ROW_BIN(3, 4, 128, extern)
+
+// The row bins of one (dimension, order): one launch per bin (two for a split bin).
 template <int D, int Q>
 int dispatch_row_bins(const Work& w, double hscale, const int32_t* bin_count, const int64_t* row_ptr,
                       const int32_t* col, double* val, int8_t* status, hipStream_t st, const BackwardArgs* bw,
