@@ -155,6 +155,25 @@ def test_full_size_counts_and_sampled_faces(c3):
     _say(f"c3 sampled {len(faces)} faces, worst rel err {worst:.2e}")
 
 
+def test_full_size_faces_of_every_row_count_in_the_split_bin(c3):
+    """The 96-row bin of this workload runs as two launches: faces with at most 88 rows on
+    an 88-row kernel instance, the rest on the 96-row one.  Three seeded faces of every
+    row count from 81 to 96 (both launches, both sides of the boundary) against the oracle."""
+    g, en, dg, b, st = c3
+    rp_g, col_g, val_g, st_g = _host(st)
+    n = np.diff(rp_g)
+    rng = np.random.default_rng(11)
+    faces, seen = [], []
+    for rows in range(81, 97):
+        cand = np.nonzero(n == rows)[0]
+        if len(cand):
+            seen.append(rows)
+            faces.extend(rng.choice(cand, min(3, len(cand)), replace=False))
+    assert any(r <= 88 for r in seen) and any(r > 88 for r in seen)
+    worst = _check_faces(g, en, 3, faces, rp_g, col_g, val_g, st_g)
+    _say(f"c3 split bin: {len(faces)} faces with {seen[0]}..{seen[-1]} rows, worst rel err {worst:.2e}")
+
+
 def test_full_size_rows_sorted_and_in_range(c3):
     g, en, dg, b, st = c3
     rp_g, col_g, val_g, st_g = _host(st)
