@@ -580,23 +580,25 @@ int volume_tables(const Work& w, const cutcell_opts& o, long long n_vol_total, i
 // binning by row count: buckets of 16 rows (N <= 16, ..., <= 128) and one bucket for
 // faces with fewer rows than monomials; perm lists faces bucket by bucket
 
-// per-block histograms in LDS (buckets, then the lower halves of the row bins), one
-// global atomic per counter per block
+// per-block histograms in LDS (buckets, then parts 0 and 1 of the row bins), one global
+// atomic per counter per block
 __global__ __launch_bounds__(256) void k_bin_count(long long n_face, int M, const int32_t* __restrict__ nrows,
                                                    const int32_t* __restrict__ tmpl, int32_t* bins) {
-  __shared__ int32_t h[kNBuckets + kMaxBins];
-  if (threadIdx.x < kNBuckets + kMaxBins) h[threadIdx.x] = 0;
+  constexpr int NP = 2 * kMaxBins;
+  __shared__ int32_t h[kNBuckets + NP];
+  if (threadIdx.x < kNBuckets + NP) h[threadIdx.x] = 0;
   __syncthreads();
   long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (f < n_face) {
     const int b = face_bucket(f, M, nrows, tmpl);
     atomicAdd(&h[b], 1);
-    if (face_lower_half(b, f, nrows)) atomicAdd(&h[kNBuckets + b], 1);
+    const int part = face_part(b, f, nrows);
+    if (part < 2) atomicAdd(&h[kNBuckets + part * kMaxBins + b], 1);
   }
   __syncthreads();
   if (threadIdx.x < kNBuckets && h[threadIdx.x]) atomicAdd(&bins[threadIdx.x], h[threadIdx.x]);
-  if (threadIdx.x < kMaxBins && h[kNBuckets + threadIdx.x])
-    atomicAdd(&bins[kHalfWords + threadIdx.x], h[kNBuckets + threadIdx.x]);
+  if (threadIdx.x < NP && h[kNBuckets + threadIdx.x])
+    atomicAdd(&bins[kPartWords + threadIdx.x], h[kNBuckets + threadIdx.x]);
 }
 
 __global__ void k_bin_starts(int32_t* bins) {
@@ -639,7 +641,7 @@ int rows_per_face(const Work& w, long long n_face, const int64_t* row_ptr, hipSt
 
 int bin_faces(const Work& w, long long n_face, int M, const int32_t* tmpl, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins, (long long)(2 * kNBuckets), 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins + kHalfWords, (long long)kMaxBins, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.bins + kPartWords, (long long)(2 * kMaxBins), 0);
   if (n_face <= 0) return CUTCELL_OK;
   hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n_face, 256)), dim3(256), 0, st, n_face, M, w.nrows, tmpl, w.bins);
   hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, st, w.bins);

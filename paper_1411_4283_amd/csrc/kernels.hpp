@@ -12,8 +12,8 @@ constexpr int kMaxBins = 8;     // row-count bins of 16 rows: N <= 16, 32, ..., 
 constexpr int kBinRows = 16;
 constexpr int kMaxRows = kMaxBins * kBinRows;
 constexpr int kNBuckets = kMaxBins + 2;   // then faces with N < M, then template copies
-constexpr int kHalfWords = 2 * kNBuckets + 1;  // counts, cursors, max rows; then per row bin
-constexpr int kBinWords = kHalfWords + kMaxBins;  // the faces in its lower half
+constexpr int kPartWords = 2 * kNBuckets + 1;      // counts, cursors, max rows; then per row bin
+constexpr int kBinWords = kPartWords + 2 * kMaxBins;  // the faces of its part 0 and of its part 1
 constexpr int kXcds = 8;        // MI355X: workgroups are dealt to 8 XCDs (own L2 each) in turn
 
 // Per-batch workspace: pointers into the caller's buffer.
@@ -52,7 +52,7 @@ struct Work {
   int64_t* scan64;      // int64 scan tiles over G*maxface
   int64_t* rp_tmp;      // [G*maxface + 1] row offsets when the caller has none (query)
   int32_t* perm;        // [G*maxface]
-  int32_t* bins;        // [kBinWords] bucket counts, bucket cursors, max rows, lower halves
+  int32_t* bins;        // [kBinWords] bucket counts, bucket cursors, max rows, part counts
   int32_t* flagged;     // [1]
   GeomPtrs* geoms;      // [G]
   size_t bytes;
@@ -109,10 +109,14 @@ __host__ __device__ inline int face_bucket(long long f, int M, const int32_t* nr
   const int N = nrows[f];
   return (N < M) ? kMaxBins : ((N - 1) / kBinRows < kMaxBins - 1 ? (N - 1) / kBinRows : kMaxBins - 1);
 }
-// face f of row bin `bucket` has at most 16 bucket + 8 rows (the lower half of the bin,
-// which comes first in the processing order and may be solved by a narrower kernel)
-__host__ __device__ inline bool face_lower_half(int bucket, long long f, const int32_t* nrows) {
-  return bucket < kMaxBins && nrows[f] <= kBinRows * bucket + kBinRows / 2;
+// part of face f in row bin `bucket` (rows 16 bucket + 1 .. 16 bucket + 16): 0 for at most
+// 8 rows above the bin's lower edge, 1 for at most 12, else 2 (and 2 outside the row bins).
+// The parts come in this order in the bin, and parts 0 and 1 may be solved by narrower
+// kernel instances.
+__host__ __device__ inline int face_part(int bucket, long long f, const int32_t* nrows) {
+  if (bucket >= kMaxBins) return 2;
+  const int above = nrows[f] - kBinRows * bucket;
+  return above <= kBinRows / 2 ? 0 : (above <= 3 * kBinRows / 4 ? 1 : 2);
 }
 // faces whose systems are bitwise those of one solved face per (geometry, direction)
 int find_templates(const Work& w, const cutcell_opts& o, long long n_face, hipStream_t st);

@@ -1,10 +1,10 @@
 // Processing order of the faces (the permutation the stencil kernels walk).  Faces are
 // grouped by bucket (16-row bins, then faces with fewer rows than monomials, then template
-// copies), a row bin's lower half (at most 8 rows above the bin below) first, and inside
-// that ordered by the cell they sit at -- a grid face's low-side
+// copies), a row bin's faces by part (at most 8, 12, 16 rows above the bin below), and
+// inside that ordered by the cell they sit at -- a grid face's low-side
 // cell (the last cell for faces on the high box side), an EB face's cut cell -- so that
 // the faces of all directions around the same cells are solved together and share the
-// rows' moments in one L2.  One stable 64-bit radix sort of (bucket, half, geometry, cell).
+// rows' moments in one L2.  One stable 64-bit radix sort of (bucket, part, geometry, cell).
 // The stencils do not depend on the order.
 #include <hipcub/hipcub.hpp>
 
@@ -12,8 +12,8 @@
 
 namespace cutcell {
 
-constexpr int kKeyBits = 45;   // 40 bits of (geometry, cell), 5 of (bucket, half)
-static_assert(2 * kNBuckets <= 32, "bucket and half must fit in 5 key bits");
+constexpr int kKeyBits = 45;   // 40 bits of (geometry, cell), 5 of (bucket, part)
+static_assert(3 * kNBuckets <= 32, "bucket and part must fit in 5 key bits");
 
 __global__ void k_face_keys(GridDims g, long long n_face, int M, const int32_t* __restrict__ fcode,
                             const int32_t* __restrict__ fref, const GeomPtrs* __restrict__ geoms,
@@ -34,7 +34,7 @@ __global__ void k_face_keys(GridDims g, long long n_face, int M, const int32_t* 
     cell = geoms[gi].eb_cell[fref[f]];
   }
   const int b = face_bucket(f, M, nrows, tmpl);
-  const unsigned long long bh = ((unsigned long long)b << 1) | (face_lower_half(b, f, nrows) ? 0ull : 1ull);
+  const unsigned long long bh = (unsigned long long)(3 * b + face_part(b, f, nrows));
   keys[f] = (bh << 40) | (unsigned long long)((long long)gi * g.ncell + cell);
   vals[f] = (int32_t)f;
 }

@@ -877,35 +877,42 @@ constexpr int pool_waves() {
   return n < 4 ? n : 4;
 }
 
-// A row bin is solved in two launches, its lower half (N <= NPAD - 8, first in the bin's
-// order) by a kernel instance for NPAD - 8 rows, when that instance fits more waves per
-// pool (3D order 4: the 96-row bin, whose regular faces have 88 rows).
-template <int D, int Q, int NPAD>
-constexpr bool split_bin() {
-  constexpr int lo = NPAD - kBinRows / 2;
-  if constexpr (lo < Dims<D, Q>::M) return false;
-  else return pool_waves<D, Q, lo>() > pool_waves<D, Q, NPAD>();
+// A narrower kernel instance of P rows pays for a part of a bin of NPAD rows when it fits
+// more waves per pool (3D order 4: 88 and 92 rows for the 96-row bin, whose regular faces
+// have 88 rows; no other bin of the orders and dimensions built).
+template <int D, int Q, int P, int NPAD>
+constexpr bool narrower_pays() {
+  if constexpr (P < Dims<D, Q>::M) return false;
+  else return pool_waves<D, Q, P>() > pool_waves<D, Q, NPAD>();
 }
 
+// One row bin: its part 0 (n0 faces, at most NPAD - 8 rows) and part 1 (n1 faces, at most
+// NPAD - 4 rows) come first in its order; each runs on the narrowest instance that pays,
+// the rest on the NPAD-row instance.  The adjoint runs the whole bin at NPAD rows.
 template <int D, int Q, int NPAD>
-void launch_row_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, long long nlo,
+void launch_row_bin(const Work& w, double hscale, const int32_t* perm, long long nbin, long long n0, long long n1,
                     const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status, hipStream_t st,
                     const BackwardArgs* bw, BinSchedule sc, bool neu, double h, double wpow) {
-  if constexpr (split_bin<D, Q, NPAD>()) {
-    if (!bw && nlo > 0) {
-      launch_bin<D, Q, NPAD - kBinRows / 2, true>(w, hscale, perm, nlo, row_ptr, col, val, status, st, bw, sc, neu, h,
-                                                  wpow);
-      launch_bin<D, Q, NPAD>(w, hscale, perm + nlo, nbin - nlo, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
-      return;
+  constexpr int P0 = NPAD - kBinRows / 2, P1 = NPAD - kBinRows / 4;
+  long long done = 0;
+  if (!bw) {
+    if constexpr (narrower_pays<D, Q, P0, NPAD>()) {
+      launch_bin<D, Q, P0, true>(w, hscale, perm, n0, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
+      done = n0;
+    }
+    if constexpr (narrower_pays<D, Q, P1, NPAD>()) {
+      launch_bin<D, Q, P1, true>(w, hscale, perm + done, n0 + n1 - done, row_ptr, col, val, status, st, bw, sc, neu,
+                                 h, wpow);
+      done = n0 + n1;
     }
   }
-  launch_bin<D, Q, NPAD>(w, hscale, perm, nbin, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
+  launch_bin<D, Q, NPAD>(w, hscale, perm + done, nbin - done, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
 }
 
 // Explicit instantiations: each (dimension, order, bin) lives in one stencil_d*q*.hip file,
 // so the library's kernels compile in parallel (the 3D order-4 bins over three files).
 #define CC_ROW_BIN(DD, QQ, P, EXT) \
-  EXT template void launch_row_bin<DD, QQ, P>(const Work&, double, const int32_t*, long long, long long, \
+  EXT template void launch_row_bin<DD, QQ, P>(const Work&, double, const int32_t*, long long, long long, long long, \
                                               const int64_t*, const int32_t*, double*, int8_t*, hipStream_t, \
                                               const BackwardArgs*, BinSchedule, bool, double, double);
 #define CC_ROW_BINS_ALL(DD, QQ, EXT) \
@@ -929,12 +936,13 @@ int dispatch_row_bins(const Work& w, double hscale, const int32_t* bin_count, co
     if (nb == 0 || (only_bin >= 0 && b != only_bin)) continue;
     const int npad = kBinRows * (b + 1);
     if (npad < M) return fail(CUTCELL_E_INVALID_ARG, "internal: face with N >= M in a bin narrower than M");
-    const long long nlo = bin_count[kHalfWords + b];
+    const long long n0 = bin_count[kPartWords + b], n1 = bin_count[kPartWords + kMaxBins + b];
     switch (npad) {
 #define CC_BIN(P) \
   case P: \
     if constexpr (M <= P) \
-      launch_row_bin<D, Q, P>(w, hscale, p, nb, nlo, row_ptr, col, val, status, st, bw, sched[b], neu, h, wpow); \
+      launch_row_bin<D, Q, P>(w, hscale, p, nb, n0, n1, row_ptr, col, val, status, st, bw, sched[b], neu, h, \
+                              wpow); \
     break;
       CC_BIN(16) CC_BIN(32) CC_BIN(48) CC_BIN(64) CC_BIN(80) CC_BIN(96) CC_BIN(112) CC_BIN(128)
 #undef CC_BIN
