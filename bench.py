@@ -498,10 +498,15 @@ def cpu_baseline(g, R, sample, seed=7, workers=None):
     if workers and workers > 1:
         many = np.random.default_rng(seed + 1).choice(en.n_face, min(4 * sample, en.n_face), replace=False)
         chunks = np.array_split(many, 8 * workers)
-        with mp.get_context("fork").Pool(workers) as pool:
+        pool = mp.get_context("fork").Pool(workers)
+        try:
             t0 = time.perf_counter()
             done = sum(pool.map(_oracle_chunk, chunks))
             tw = time.perf_counter() - t0
+        finally:
+            # every worker exits and is reaped before the GPU is touched
+            pool.close()
+            pool.join()
         out["all_cores"] = dict(value=done / tw, unit="faces/s", cores=workers,
                                 sample=f"{done} faces (seed {seed + 1}) over {workers} processes, {tw:.1f} s; "
                                        "enumeration not included")

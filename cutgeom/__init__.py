@@ -34,7 +34,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cutgeom.cpp")
 _LIB = os.path.join(_HERE, "_cutgeom.so")
 
-BALL, HALFSPACE, STAR2, SH3, SINE2, CIRCLES = range(6)
+BALL, HALFSPACE, STAR2, SH3 = range(4)
 
 
 def build(force: bool = True) -> str:
@@ -153,18 +153,6 @@ def sh_body_outside(center, r0, coef) -> Shape:
     coef = np.asarray(coef, dtype=np.float64)
     assert coef.shape == (16,)
     return Shape(SH3, 3, tuple(center) + (float(r0),) + tuple(coef.tolist()) + (1.0,))
-
-
-def sine_under(a=0.25, b=math.sqrt(2) / 2) -> Shape:
-    """Region under the curve y = a + b (1 - cos 2 pi x)."""
-    return Shape(SINE2, 2, (float(a), float(b), 1.0))
-
-
-def circles_outside(centers, r) -> Shape:
-    flat = []
-    for c in centers:
-        flat += [float(c[0]), float(c[1])]
-    return Shape(CIRCLES, 2, (float(len(centers)), float(r)) + tuple(flat) + (1.0,))
 
 
 # ---------------------------------------------------------------------------------

@@ -25,7 +25,7 @@
 
 namespace {
 
-enum Kind { BALL = 0, HALFSPACE = 1, STAR2 = 2, SH3 = 3, SINE2 = 4, CIRCLES = 5 };
+enum Kind { BALL = 0, HALFSPACE = 1, STAR2 = 2, SH3 = 3 };
 
 struct Shape {
   int kind = 0, dim = 2;
@@ -35,9 +35,6 @@ struct Shape {
   int k = 0;                    // star petals
   double nrm[3] = {0, 0, 0}, off = 0;   // half-space phi0 = n.x - off
   double sh[16] = {0};          // SH body: R(u) = r + sum sh[j] Y_j(u)
-  double cc[8][2] = {{0}};      // circles
-  int ncirc = 0;
-  double sa = 0, sb = 0;        // sine curve y = sa + sb (1 - cos 2 pi x)
   double H = 0;                 // bound on the Hessian norm of phi0
   bool radial = false;          // star-shaped about c: phi0 < 0 iff rho < R(u)
   double Rmin = 0, Rmax = 0;
@@ -129,28 +126,6 @@ double phi0(const Shape& S, const double* x, double* g) {
       }
       return rho - R;
     }
-    case SINE2: {
-      const double w = 2 * M_PI;
-      if (g) {
-        g[0] = S.sb * w * std::sin(w * x[0]);
-        g[1] = -1.0;
-      }
-      return S.sa + S.sb * (1 - std::cos(w * x[0])) - x[1];
-    }
-    case CIRCLES: {
-      double best = 1e300;
-      int bi = 0;
-      for (int i = 0; i < S.ncirc; ++i) {
-        double dx = x[0] - S.cc[i][0], dy = x[1] - S.cc[i][1];
-        double v = (dx * dx + dy * dy - S.r * S.r) / (2 * S.r);
-        if (v < best) { best = v; bi = i; }
-      }
-      if (g) {
-        g[0] = (x[0] - S.cc[bi][0]) / S.r;
-        g[1] = (x[1] - S.cc[bi][1]) / S.r;
-      }
-      return best;
-    }
   }
   return 0;
 }
@@ -188,25 +163,6 @@ void psi_bounds(const Shape& S, const double* lo, const double* hi, double& vmin
       vmin = vmax = S.fsign;
       return;
     }
-  }
-  if (S.kind == CIRCLES) {
-    // phi0 = min_i phi_i; bound each (quadratic, exact Hessian 1/r) and take the min
-    double lo0 = 1e300, hi0 = 1e300;
-    for (int i = 0; i < S.ncirc; ++i) {
-      double mn = 0, mx = 0;
-      for (int d = 0; d < 2; ++d) {
-        double a = lo[d] - S.cc[i][d], b = hi[d] - S.cc[i][d];
-        double n = (a > 0) ? a : ((b < 0) ? -b : 0.0);
-        double f = std::max(std::fabs(a), std::fabs(b));
-        mn += n * n;
-        mx += f * f;
-      }
-      double l = (mn - S.r * S.r) / (2 * S.r), h = (mx - S.r * S.r) / (2 * S.r);
-      lo0 = std::min(lo0, l);
-      hi0 = std::min(hi0, h);
-    }
-    if (S.fsign > 0) { vmin = lo0; vmax = hi0; } else { vmin = -hi0; vmax = -lo0; }
-    return;
   }
   double m[3] = {0, 0, 0}, rr[3] = {0, 0, 0}, g[3] = {0, 0, 0};
   for (int d = 0; d < D; ++d) {
@@ -623,21 +579,6 @@ bool init_shape(Shape& S, int kind, int dim, const double* p, int np) {
       S.fsign = p[20];
       S.radial = true;
       break;
-    case SINE2:
-      if (np < 3 || dim != 2) return false;
-      S.sa = p[0]; S.sb = p[1]; S.fsign = p[2];
-      S.H = std::fabs(S.sb) * 4 * M_PI * M_PI;
-      return true;
-    case CIRCLES: {
-      if (np < 2 || dim != 2) return false;
-      S.ncirc = (int)p[0];
-      S.r = p[1];
-      if (S.ncirc < 1 || S.ncirc > 8 || np < 3 + 2 * S.ncirc) return false;
-      for (int i = 0; i < S.ncirc; ++i) { S.cc[i][0] = p[2 + 2 * i]; S.cc[i][1] = p[3 + 2 * i]; }
-      S.fsign = p[2 + 2 * S.ncirc];
-      S.H = 1.0 / S.r;
-      return true;
-    }
     default:
       return false;
   }

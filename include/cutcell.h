@@ -104,8 +104,8 @@ enum {
   CUTCELL_E_BREAKDOWN = -6     /* cutcell_solve: the residual became non-finite        */
 };
 
-/* Per-face status (Sec. 2.2.1 asks for "sufficiently many neighbors" and a full-rank
- * system; a face that has neither gets val = 0 and one of these codes). */
+/* Per-face status.  Sec. 2.2.1 assumes enough neighbours for a full-rank system; a face
+ * without them gets val = 0 and one of these codes. */
 enum {
   CUTCELL_STATUS_OK = 0,
   CUTCELL_STATUS_INSUFFICIENT_ROWS = 1, /* fewer rows than monomials (N < M)            */

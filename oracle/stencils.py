@@ -16,7 +16,16 @@ s~ = W (A~^T W)^+ F~, and the physical stencil is s = h^(D-2) s~, because scalin
 columns of A and the entries of F by h^|p| leaves both A^T s = F and the
 minimised norm ||W^-1 s|| unchanged.
 
-Readings of points the paper leaves open are tagged R1..R9 (listed in the design
+Arithmetic.  The inputs (moments) are FP64 numbers, taken as exact.  Everything the
+stencil is computed from them with -- the offsets (x_i - x0)/h, the weights, the
+re-centred rows and the factorisation -- is carried in x87 extended precision
+(numpy.longdouble, unit roundoff 5.4e-20) and rounded to FP64 once at the end: the
+oracle's own error on a face is then about cond * 1e-19, far below the 1e-11 at which
+stencils are compared, for every system of condition number up to ~1e7.  The offsets are
+formed in units of h from cell and lattice indices, so for grid and box faces they are the
+exact half-integers the geometry defines, whatever h is.
+
+Readings of points the paper leaves open are tagged R1..R16 (listed in the design
 notes); they are the same for the HIP library.
 """
 
@@ -35,9 +44,13 @@ STATUS_INSUFFICIENT_ROWS = 1
 STATUS_RANK_DEFICIENT = 2
 STATUS_NONFINITE = 3
 
-# A face is flagged rank deficient when the triangular factor of its column-equilibrated
-# weighted matrix has min|R_kk| <= RANK_TOL * max|R_kk| (reading R8).
-RANK_TOL = 1e-7
+# A face is flagged rank deficient when the triangular factor of the Householder QR of
+# its column-equilibrated weighted matrix has min|R_kk| <= RANK_TOL * max|R_kk| (reading
+# R8: Sec. 2.2.1 assumes a full-rank system; at this ratio an FP64 system no longer fixes
+# its stencil to better than about 1e-4).
+RANK_TOL = 1e-12
+
+LD = np.longdouble
 
 KIND_GRID, KIND_BOX, KIND_EB = 0, 1, 2
 
@@ -95,6 +108,8 @@ class Enumeration:
     vol_box: list = field(repr=False, default=None)    # box faces (Phi-order index) of each volume
     row_mom: np.ndarray = field(repr=False, default=None)  # moments of each Phi row about its centre
     row_ctr: np.ndarray = field(repr=False, default=None)  # centre x_i of each Phi row
+    row_ctr_h: np.ndarray = field(repr=False, default=None)  # the same in units of h (exact
+                                                              # half-integers)
 
     @property
     def n_vol(self):
@@ -214,9 +229,9 @@ def enumerate_geometry(geom) -> Enumeration:
     rm = np.zeros((en.n_phi, M))
     rc = np.zeros((en.n_phi, D))
     rm[: en.n_vol] = geom.vol_mom[vol_cell]
-    rc[: en.n_vol] = (ci[:, vol_cell].T + 0.5) * h
+    rc[: en.n_vol] = ci[:, vol_cell].T + 0.5
     rm[en.n_vol: en.n_vol + ne] = geom.eb_mom
-    rc[en.n_vol: en.n_vol + ne] = (ci[:, eb_cell].T + 0.5) * h
+    rc[en.n_vol: en.n_vol + ne] = ci[:, eb_cell].T + 0.5
     monof = {q: k for k, q in enumerate(_mono(D - 1, Q))}
     o = en.n_vol + ne
     for d in range(D):
@@ -225,11 +240,12 @@ def enumerate_geometry(geom) -> Enumeration:
         for a, k in embed:
             rm[o + sel, a] = geom.face_mom[d][box_face[sel], k]
         j = np.array(np.unravel_index(box_face[sel], _face_lattice(n, d), order="F")).T.astype(np.float64)
-        x = (j + 0.5) * h
-        x[:, d] = j[:, d] * h
+        x = j + 0.5
+        x[:, d] = j[:, d]
         rc[o + sel] = x
     en.row_mom = rm
-    en.row_ctr = rc
+    en.row_ctr_h = rc
+    en.row_ctr = rc * h
     return en
 
 
@@ -272,23 +288,29 @@ def neighbours(en: Enumeration, f: int, R: int) -> np.ndarray:
 # Sec. 2.2.1: rows of A, the weights and the flux vector
 
 
-def face_centre(en: Enumeration, f: int, eb_x0: str = "centroid") -> np.ndarray:
-    """x0 of face f (Sec. 2.4): the face centre for a grid-aligned face; for an EB face
-    the centre of the cell it cuts, read as the centroid of the cut volume (reading R3;
+def face_centre_h(en: Enumeration, f: int, eb_x0: str = "centroid") -> np.ndarray:
+    """x0 / h of face f (Sec. 2.4), in extended precision: the face centre for a
+    grid-aligned face; for an EB face the centre of the cell it cuts, read as the
+    centroid of the cut volume, c + (first moments / zeroth moment) (reading R3;
     ``eb_x0="cell"`` takes the Cartesian cell centre instead, the literal reading, which
     gives an operator with positive eigenvalues on the paper's circle)."""
     if en.face_kind[f] == KIND_EB:
         v = int(en.face_lo[f])
-        c = en.row_ctr[v].copy()
+        c = en.row_ctr_h[v].astype(LD)
         if eb_x0 == "cell":
             return c
-        m = en.row_mom[v]
-        return c + en.h * m[1 : en.D + 1] / m[0]
+        m = en.row_mom[v].astype(LD)
+        return c + m[1 : en.D + 1] / m[0]
     d = int(en.face_dir[f])
-    j = np.array(np.unravel_index(int(en.face_lin[f]), _face_lattice(en.n, d), order="F"), dtype=np.float64)
-    x = (j + 0.5) * en.h
-    x[d] = j[d] * en.h
+    j = np.array(np.unravel_index(int(en.face_lin[f]), _face_lattice(en.n, d), order="F"), dtype=LD)
+    x = j + LD(0.5)
+    x[d] = j[d]
     return x
+
+
+def face_centre(en: Enumeration, f: int, eb_x0: str = "centroid") -> np.ndarray:
+    """x0 of face f in physical coordinates (FP64), see face_centre_h."""
+    return (face_centre_h(en, f, eb_x0) * LD(en.h)).astype(np.float64)
 
 
 def recentre(mom: np.ndarray, delta: np.ndarray, D: int, Q: int) -> np.ndarray:
@@ -296,18 +318,30 @@ def recentre(mom: np.ndarray, delta: np.ndarray, D: int, Q: int) -> np.ndarray:
     m^p(x0) = sum_{q <= p} C(p,q) delta^(p-q) m^q(c),  delta = (c - x0)/h, scaled.
     ``mom`` is [..., M], ``delta`` is [..., D]."""
     coef, ex, qi, P = _shift_terms(D, Q)
-    powers = np.prod(delta[..., None, :] ** ex, axis=-1)          # [..., T]
-    return (coef * powers * mom[..., qi]) @ P
+    # delta_d^k for k = 0..Q by repeated products, then the product over the directions
+    pw = [np.ones_like(delta)]
+    for _ in range(Q):
+        pw.append(pw[-1] * delta)
+    pw = np.stack(pw, axis=-1)                                    # [..., D, Q+1]
+    powers = pw[..., 0, ex[:, 0]]
+    for d in range(1, D):
+        powers = powers * pw[..., d, ex[:, d]]                    # [..., T]
+    # the terms come grouped by p (ascending), so each m^p(x0) is the sum of one run
+    starts = np.searchsorted(np.argmax(P, axis=1), np.arange(P.shape[1]))
+    return np.add.reduceat(coef * powers * mom[..., qi], starts, axis=-1)
 
 
 def row_weights(dist_over_h: np.ndarray, wpow: float = 5.0) -> np.ndarray:
     """W_ii of Sec. 2.4: 1 if |x_i - x0|/h < 1/2, else (2 |x_i - x0|/h)^-5; `wpow`
     replaces the exponent 5 for weight studies (0: unweighted least squares)."""
-    d = np.asarray(dist_over_h, dtype=np.float64)
-    return np.where(d < 0.5, 1.0, (2.0 * np.maximum(d, 0.5)) ** -float(wpow))
+    d = np.asarray(dist_over_h)
+    if d.dtype != LD:
+        d = d.astype(np.float64)
+    one = d.dtype.type(1)
+    return np.where(d < 0.5, one, (2 * np.maximum(d, d.dtype.type(0.5))) ** (-d.dtype.type(wpow)))
 
 
-def flux_vector(geom, en: Enumeration, f: int, x0: np.ndarray) -> np.ndarray:
+def flux_vector(geom, en: Enumeration, f: int, x0h: np.ndarray) -> np.ndarray:
     """Scaled flux vector F~_p = int_f grad(xi^p) . n dA_xi, xi = (x - x0)/h (Sec. 2.2).
 
     Grid/box face of direction d (reference normal +e_d, x0 the face centre, so the face
@@ -315,12 +349,12 @@ def flux_vector(geom, en: Enumeration, f: int, x0: np.ndarray) -> np.ndarray:
     p_d = 1, so F~_p = face moment of exponent p - e_d.  EB face (normal out of the
     fluid): F~_p = sum_d p_d (EB normal moment of exponent p - e_d, component d) about
     x0 (the identity used in Sec. 2.3); the stored normal moments, taken about the cell
-    centre, are re-centred to x0."""
+    centre, are re-centred to x0 (x0h = x0 / h, extended precision)."""
     D, Q = en.D, en.Q
     mono = _mono(D, Q)
-    F = np.zeros(len(mono))
+    F = np.zeros(len(mono), dtype=LD)
     if en.face_kind[f] == KIND_EB:
-        return eb_normal_flux(geom, en, int(en.face_lin[f]), x0)
+        return eb_normal_flux(geom, en, int(en.face_lin[f]), x0h)
     d = int(en.face_dir[f])
     monof = {q: k for k, q in enumerate(_mono(D - 1, Q))}
     for a, p in enumerate(mono):
@@ -329,16 +363,17 @@ def flux_vector(geom, en: Enumeration, f: int, x0: np.ndarray) -> np.ndarray:
     return F
 
 
-def eb_normal_flux(geom, en: Enumeration, e: int, x0: np.ndarray) -> np.ndarray:
+def eb_normal_flux(geom, en: Enumeration, e: int, x0h: np.ndarray) -> np.ndarray:
     """sum_d p_d (normal moment of exponent p - e_d, component d) of EB face e about x0,
     scaled: the flux of each monomial xi^p through the face (Sec. 2.3), and, divided by
     the face area, the Neumann row of eq. 'Neu moment eq for cp'.  The stored normal
-    moments, taken about the cell centre, are re-centred to x0 by the binomial theorem."""
+    moments, taken about the cell centre, are re-centred to x0 by the binomial theorem
+    (x0h = x0 / h; extended precision)."""
     D, Q = en.D, en.Q
     mono = _mono(D, Q)
-    F = np.zeros(len(mono))
-    c = en.row_ctr[en.n_vol + e]
-    nu = recentre(geom.eb_nmom[e], np.broadcast_to((c - x0) / en.h, (D, D)), D, Q - 1)   # [D, M1]
+    F = np.zeros(len(mono), dtype=LD)
+    c = en.row_ctr_h[en.n_vol + e].astype(LD)
+    nu = recentre(geom.eb_nmom[e].astype(LD), np.broadcast_to(c - x0h, (D, D)), D, Q - 1)   # [D, M1]
     mono1 = {q: k for k, q in enumerate(_mono(D, Q - 1))}
     for a, p in enumerate(mono):
         for d in range(D):
@@ -349,9 +384,10 @@ def eb_normal_flux(geom, en: Enumeration, e: int, x0: np.ndarray) -> np.ndarray:
     return F
 
 
-def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet",
-                wpow: float = 5.0):
-    """Rows A~ (N x M), weights W (N), flux vector F~ (M) and the Phi indices of face f.
+def face_system_ld(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet",
+                   wpow: float = 5.0):
+    """Rows A~ (N x M), weights W (N), flux vector F~ (M) and the Phi indices of face f,
+    in extended precision (see the module notes).
 
     Rows follow eq. 'volume moment eq for cp' (volume averages: A_vp = m^p_v(x0)/m^0_v)
     and eq. 'Dir moment eq for cp' (Dirichlet boundary faces: b_p = m^p(x0)/m^0); the
@@ -361,27 +397,81 @@ def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", 
     variables xi = (x - x0)/h this row is h times the physical one).  Box faces are always
     Dirichlet."""
     idx = neighbours(en, f, R)
-    x0 = face_centre(en, f, eb_x0)
-    mom = en.row_mom[idx]                       # [N, M]
-    delta = (en.row_ctr[idx] - x0) / en.h       # [N, D]
+    x0h = face_centre_h(en, f, eb_x0)
+    mom = en.row_mom[idx].astype(LD)            # [N, M]
+    delta = en.row_ctr_h[idx].astype(LD) - x0h  # [N, D], (x_i - x0)/h
     A = recentre(mom, delta, en.D, en.Q) / mom[:, :1]
     if eb_bc == "neumann":
         for i, k in enumerate(idx):
             if en.n_vol <= k < en.n_vol + en.n_eb:
                 e = int(k - en.n_vol)
-                A[i] = eb_normal_flux(geom, en, e, x0) / geom.eb_mom[e, 0]
+                A[i] = eb_normal_flux(geom, en, e, x0h) / LD(geom.eb_mom[e, 0])
     elif eb_bc != "dirichlet":
         raise ValueError(eb_bc)
     W = row_weights(np.sqrt(np.sum(delta * delta, axis=1)), wpow)
-    F = flux_vector(geom, en, f, x0)
+    F = flux_vector(geom, en, f, x0h)
     return A, W, F, idx
+
+
+def face_system(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet",
+                wpow: float = 5.0):
+    """face_system_ld rounded to FP64: rows A~ (N x M), weights W (N), flux vector F~ (M)
+    and the Phi indices of face f."""
+    A, W, F, idx = face_system_ld(geom, en, f, R, eb_x0, eb_bc, wpow)
+    return A.astype(np.float64), W.astype(np.float64), F.astype(np.float64), idx
+
+
+def householder_qr(B: np.ndarray):
+    """Householder QR of B (N x M, N >= M) in the dtype of B, in LAPACK's conventions:
+    reflector k is H_k = I - tau_k v_k v_k^T with v_k zero above row k and 1 at row k,
+    chosen so that H_k maps the column below the diagonal, x, onto beta_k e_k with
+    beta_k = -sign(x_k) ||x|| (tau_k = 0, H_k = I when x has no entries below row k);
+    B = H_0 H_1 ... H_{M-1} [R; 0].  Returns (V [N, M], tau [M], R [M, M])."""
+    N, M = B.shape
+    T = B.dtype.type
+    C = B.copy()
+    V = np.zeros_like(B)
+    tau = np.zeros(M, dtype=B.dtype)
+    for k in range(M):
+        x = C[k:, k]
+        alpha = x[0]
+        sigma = np.sqrt(np.sum(x[1:] * x[1:]))
+        V[k, k] = 1
+        if sigma == 0:
+            continue
+        beta = -np.copysign(np.sqrt(alpha * alpha + sigma * sigma), alpha)
+        tau[k] = (beta - alpha) / beta
+        V[k + 1:, k] = x[1:] / (alpha - beta)
+        v = V[k:, k]
+        C[k:, k + 1:] -= tau[k] * np.outer(v, v @ C[k:, k + 1:])
+        C[k, k] = beta
+        C[k + 1:, k] = T(0)
+    return V, tau, np.triu(C[:M])
+
+
+def min_norm_solve(V: np.ndarray, tau: np.ndarray, R: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """The z of least 2-norm with B^T z = F, from the Householder QR of B: with
+    B = Q1 R, B^T z = R^T (Q1^T z), so z = Q1 u with R^T u = F (forward substitution),
+    and Q1 u = H_0 ... H_{M-1} [u; 0] (the reflectors applied last to first)."""
+    N, M = V.shape
+    u = np.zeros(M, dtype=V.dtype)
+    for k in range(M):
+        u[k] = (F[k] - R[:k, k] @ u[:k]) / R[k, k]
+    z = np.zeros(N, dtype=V.dtype)
+    z[:M] = u
+    for k in range(M - 1, -1, -1):
+        v = V[k:, k]
+        z[k:] -= tau[k] * v * (v @ z[k:])
+    return z
 
 
 def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid", eb_bc: str = "dirichlet",
                  wpow: float = 5.0):
     """Stencil of face f: s = h^(D-2) W (A~^T W)^+ F~ (eq. 'stencil equation solution'),
-    the solution of A~^T s~ = F~ of least ||W^-1 s~|| (Sec. 2.2.1).  The pseudo-inverse
-    is applied as LAPACK's minimum-norm least-squares solve.  Under Neumann EB conditions
+    the solution of A~^T s~ = F~ of least ||W^-1 s~|| (Sec. 2.2.1): with B = W A~ and
+    z = W^-1 s~, z is the minimum-norm solution of B^T z = F~, computed from a Householder
+    QR of B with its columns scaled to unit 2-norm (the scaling E changes B^T z = F~ into
+    (B E)^T z = E F~, the same z), in extended precision.  Under Neumann EB conditions
     the values of the EB (normal-derivative) rows carry h^(D-1) instead of h^(D-2), and an
     EB face's own flux is its prescribed data: the single entry |A_f| on its Phi entry
     (reading: the paper does not say how the flux of a Neumann face is formed).
@@ -390,9 +480,9 @@ def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid",
         e = int(en.face_lin[f])
         return (np.array([en.n_vol + e], np.int64), np.array([geom.eb_mom[e, 0] * en.h ** (en.D - 1)]),
                 STATUS_OK)
-    A, W, F, idx = face_system(geom, en, f, R, eb_x0, eb_bc, wpow)
+    A, W, F, idx = face_system_ld(geom, en, f, R, eb_x0, eb_bc, wpow)
     N, M = A.shape
-    if not (np.all(np.isfinite(A)) and np.all(np.isfinite(F))):
+    if not (np.all(np.isfinite(A)) and np.all(np.isfinite(F)) and np.all(np.isfinite(W))):
         return idx, np.zeros(N), STATUS_NONFINITE
     if N < M:
         return idx, np.zeros(N), STATUS_INSUFFICIENT_ROWS
@@ -400,14 +490,15 @@ def face_stencil(geom, en: Enumeration, f: int, R: int, eb_x0: str = "centroid",
     cn = np.sqrt(np.sum(B * B, axis=0))
     if np.any(cn == 0):
         return idx, np.zeros(N), STATUS_RANK_DEFICIENT
-    r = np.abs(np.diag(np.linalg.qr(B / cn, mode="r")))
+    V, tau, Rm = householder_qr(B / cn)
+    r = np.abs(np.diag(Rm))
     if r.min() <= RANK_TOL * r.max():
         return idx, np.zeros(N), STATUS_RANK_DEFICIENT
-    y = np.linalg.lstsq(A.T * W[None, :], F, rcond=None)[0]
-    hs = np.full(N, en.h ** (en.D - 2))
+    z = min_norm_solve(V, tau, Rm, F / cn)
+    hs = np.full(N, LD(en.h) ** (en.D - 2), dtype=LD)
     if eb_bc == "neumann":
-        hs[(idx >= en.n_vol) & (idx < en.n_vol + en.n_eb)] *= en.h
-    return idx, hs * W * y, STATUS_OK
+        hs[(idx >= en.n_vol) & (idx < en.n_vol + en.n_eb)] *= LD(en.h)
+    return idx, (hs * W * z).astype(np.float64), STATUS_OK
 
 
 def face_condition(geom, en: Enumeration, f: int, R: int, eb_bc: str = "dirichlet", wpow: float = 5.0) -> float:
