@@ -120,14 +120,9 @@ def workload(name):
 
 
 def c4_shapes(w):
-    import numpy as np
-
     import cutgeom as cg
 
-    rng = np.random.default_rng(w["seed"])
-    centres = 0.5 + rng.uniform(-0.05, 0.05, (w["n_geom"], 3))
-    radii = rng.uniform(0.25, 0.35, w["n_geom"])
-    return [cg.ball_outside(tuple(float(v) for v in c), float(r)) for c, r in zip(centres, radii)]
+    return cg.perturbed_spheres(w["n_geom"], w["seed"])
 
 
 def batched_comparison(steps):
@@ -454,8 +449,9 @@ def solve_timings(torch, cc, g, st, apply_ms, rtol=1e-12, restart=50, lap=None):
             "preconditioner": "Jacobi (right)", "matvec": "volume matrix" if lap is not None else "face fluxes"}
 
 
-def _oracle_chunk(faces):
-    """Worker: the oracle's stencil + face flux for a list of faces (one thread)."""
+def _oracle_chunk(faces, keep=None):
+    """Worker: the oracle's stencil + face flux for a list of faces (one thread).  With a
+    dict `keep`, the stencils are stored in it by face."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -466,14 +462,29 @@ def _oracle_chunk(faces):
         for f in faces:
             idx, sv, st = oracle.face_stencil(g, en, int(f), R)
             _ = float(np.dot(sv, phi[idx]))
+            if keep is not None:
+                keep[int(f)] = (sv, int(st))
     return len(faces)
 
 
+def _cond_chunk(faces):
+    """Worker: condition numbers of the column-equilibrated W A of a list of faces."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    g, en, R = (_ORACLE_STATE[k] for k in ("g", "en", "R"))
+    with threadpool_limits(limits=1):
+        return [oracle.face_condition(g, en, int(f), R) for f in faces]
+
+
 def cpu_baseline(g, R, sample, seed=7, workers=None):
-    """The oracle (plain FP64 numpy) on a random sample of faces: build (neighbours, rows,
-    weights, stencil) plus each face's flux in the apply, and the enumeration pro rata.
-    One thread, and (if `workers` > 1) the same per-face work spread over that many
-    forked worker processes.  Runs before the GPU is touched.  Returns the result dict."""
+    """The oracle (numpy, extended-precision Householder QR per face) on a random sample of
+    faces: build (neighbours, rows, weights, stencil) plus each face's flux in the apply, and
+    the enumeration pro rata.  One thread, and (if `workers` > 1) the same per-face work
+    spread over that many forked worker processes, which also compute the sample's
+    condition numbers.  Runs before the GPU is touched.  Returns the result dict and
+    (faces, their oracle stencils, their condition numbers or None)."""
     import multiprocessing as mp
 
     import numpy as np
@@ -488,13 +499,15 @@ def cpu_baseline(g, R, sample, seed=7, workers=None):
     faces = np.random.default_rng(seed).choice(en.n_face, min(sample, en.n_face), replace=False)
     phi = np.random.default_rng(2).standard_normal(en.n_phi)
     _ORACLE_STATE.update(g=g, en=en, R=R, phi=phi)
+    kept = {}
     t0 = time.perf_counter()
-    _oracle_chunk(faces)
+    _oracle_chunk(faces, kept)
     t_faces = time.perf_counter() - t0
     t = t_faces + t_enum * len(faces) / en.n_face
     out = dict(value=len(faces) / t, unit="faces/s", cores=1, kind="oracle",
                sample=f"{len(faces)} faces drawn uniformly (seed {seed}) of {en.n_face}; stencil build + "
                       f"face flux per face, enumeration pro rata; {t:.1f} s on one thread")
+    conds = None
     if workers and workers > 1:
         many = np.random.default_rng(seed + 1).choice(en.n_face, min(4 * sample, en.n_face), replace=False)
         chunks = np.array_split(many, 8 * workers)
@@ -503,6 +516,8 @@ def cpu_baseline(g, R, sample, seed=7, workers=None):
             t0 = time.perf_counter()
             done = sum(pool.map(_oracle_chunk, chunks))
             tw = time.perf_counter() - t0
+            # condition numbers of the timed sample's systems (not timed), for the parity report
+            conds = np.concatenate([np.asarray(c) for c in pool.map(_cond_chunk, np.array_split(faces, 4 * workers))])
         finally:
             # every worker exits and is reaped before the GPU is touched
             pool.close()
@@ -511,7 +526,69 @@ def cpu_baseline(g, R, sample, seed=7, workers=None):
                                 sample=f"{done} faces (seed {seed + 1}) over {workers} processes, {tw:.1f} s; "
                                        "enumeration not included")
     out["host"] = host_info()
+    return out, (faces, kept, conds)
+
+
+def parity_report(st, ref):
+    """The timed build's stencils on the oracle's timed sample of faces: worst relative error
+    per face (max over the row against the row's largest oracle value), status agreement,
+    and the condition numbers of those faces' equilibrated W A."""
+    import numpy as np
+
+    faces, kept, conds = ref
+    rp = st.row_ptr.cpu().numpy()
+    val = st.val.cpu().numpy()
+    status = st.status.cpu().numpy()
+    worst, wf, mism = 0.0, -1, 0
+    for f in faces:
+        f = int(f)
+        sv, so = kept[f]
+        if status[f] != so:
+            mism += 1
+            continue
+        if so != 0:
+            continue
+        err = float(np.abs(val[rp[f]:rp[f + 1]] - sv).max() / np.abs(sv).max())
+        if err > worst:
+            worst, wf = err, f
+    out = {"faces": int(len(faces)), "worst_rel_err": worst, "worst_face": wf, "status_mismatches": mism,
+           "bar": 1e-11}
+    if conds is not None:
+        out["cond"] = {f"p{q}": float(np.percentile(conds, q)) for q in (50, 90, 99)}
+        out["cond"]["max"] = float(np.max(conds))
+        if wf >= 0:
+            out["cond_of_worst_face"] = float(conds[list(map(int, faces)).index(wf)])
     return out
+
+
+def qr_all_timings(torch, cc, dg, R, st_ref, n_face, flops, reps=2):
+    """The same build with every face solved by Householder QR (double-double rows and
+    refinement residuals): time per build and its stencils against the default build's."""
+    b = cc.Builder(dg, R, factorization="qr")
+    st = b.allocate()
+    b.build(out=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.build(out=st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    nnz = int(st.sizes.nnz)
+    rp = st_ref.row_ptr
+    face = torch.repeat_interleave(torch.arange(n_face, device=rp.device), rp[1:] - rp[:-1])
+    diff = (st.val[:nnz] - st_ref.val[:nnz]).abs()
+    dmax = torch.zeros(n_face, dtype=torch.float64, device=rp.device).scatter_reduce_(0, face, diff, "amax")
+    smax = torch.zeros(n_face, dtype=torch.float64, device=rp.device).scatter_reduce_(0, face,
+                                                                                       st_ref.val[:nnz].abs(), "amax")
+    ok = smax > 0
+    rel = float((dmax[ok] / smax[ok]).max())
+    same_status = bool(torch.equal(st.status[:n_face], st_ref.status[:n_face]))
+    del b, st, face, diff, dmax, smax
+    torch.cuda.empty_cache()
+    return {"ms_per_build": ms, "faces_per_s": n_face / (ms * 1e-3), "tflops_lapack_count": flops / (ms * 1e-3) / 1e12,
+            "max_rel_diff_vs_default_build": rel, "same_status": same_status,
+            "note": "every face by the QR path (one wave per face, B in shared memory, double-double rows and "
+                    "residuals); the default build routes only ill-conditioned faces there"}
 
 
 def host_info():
@@ -534,7 +611,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--cpu-sample", type=int, default=8000, help="faces of the oracle's timed sample (~10 s)")
+    ap.add_argument("--cpu-sample", type=int, default=4000, help="faces of the oracle's timed sample (~12 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-geometry comparison")
     ap.add_argument("--no-autotune", action="store_true")
@@ -543,6 +620,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip timing the GPU Poisson solve")
     ap.add_argument("--no-laplacian", action="store_true", help="skip the volume-matrix build and apply")
     ap.add_argument("--no-weight-study", action="store_true", help="skip the weight-exponent study and spectra")
+    ap.add_argument("--no-qr-all", action="store_true", help="skip timing the build with every face by QR")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 256 MiB device copy (reference kernel for rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -563,7 +641,7 @@ def main():
     if not args.no_cpu_baseline:
         # before anything initialises the GPU: the worker processes are forks of this one
         log("cpu baseline (oracle)")
-        base = cpu_baseline(g, w["R"], args.cpu_sample, workers=min(16, os.cpu_count() or 1))
+        base, parity_ref = cpu_baseline(g, w["R"], args.cpu_sample, workers=min(16, os.cpu_count() or 1))
     regular = regular_face_count(g, w["R"]) if g.D == 3 else None
 
     import torch
@@ -621,7 +699,8 @@ def main():
     torch.cuda.synchronize()
     apply_ms = [a.elapsed_time(z) for a, z in ev2]
     ms_per_step = (t1 - t0) / args.steps * 1e3
-    log(f"ms/step {ms_per_step:.3f}  solve {np.mean(solve_ms):.3f} ms  apply {np.mean(apply_ms) * 1e3:.1f} us")
+    log(f"ms/step {ms_per_step:.3f}  solve {np.mean(solve_ms):.3f} ms  apply {np.mean(apply_ms) * 1e3:.1f} us "
+        f"({st.qr_faces} faces by QR)")
 
     rp = st.row_ptr.cpu().numpy()
     N = np.diff(rp)
@@ -683,6 +762,15 @@ def main():
         "faces_regular_note": "faces between two cells whose whole path-radius ball is plain interior volume "
                               "(fixed rows); every face, regular or not, is solved",
     }
+    out["qr_faces"] = int(st.qr_faces)
+    out["qr_faces_note"] = ("faces whose system the Gram path leaves to Householder QR (estimated cond of the "
+                            "equilibrated W A above 2e4, a pivot ratio below 1e-4, or an unsettled refinement)")
+    if base is not None:
+        out["parity_sample"] = parity_report(st, parity_ref)
+        log(f"parity sample: {out['parity_sample']}")
+    if not args.no_qr_all:
+        log("every face by Householder QR")
+        out["qr_all"] = qr_all_timings(torch, cc, dg, w["R"], st, s.n_face, flops)
     if not args.no_adjoint:
         log("adjoint timings")
         out["adjoint"] = adjoint_timings(torch, cc, b, st, phi, flux)

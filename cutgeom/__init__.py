@@ -155,6 +155,16 @@ def sh_body_outside(center, r0, coef) -> Shape:
     return Shape(SH3, 3, tuple(center) + (float(r0),) + tuple(coef.tolist()) + (1.0,))
 
 
+def perturbed_spheres(n_geom=64, seed=3) -> list:
+    """The batched workload's shapes: unit cubes minus spheres with centres
+    0.5 + U(-0.05, 0.05)^3 and radii U(0.25, 0.35), drawn from default_rng(seed), all
+    centres first, then all radii."""
+    rng = np.random.default_rng(seed)
+    centres = 0.5 + rng.uniform(-0.05, 0.05, (n_geom, 3))
+    radii = rng.uniform(0.25, 0.35, n_geom)
+    return [ball_outside(tuple(float(v) for v in c), float(r)) for c, r in zip(centres, radii)]
+
+
 # ---------------------------------------------------------------------------------
 # geometry
 

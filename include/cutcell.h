@@ -88,7 +88,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 10
+#define CUTCELL_ABI_VERSION 11
 
 enum {
   CUTCELL_OK = 0,
@@ -109,8 +109,9 @@ enum {
 enum {
   CUTCELL_STATUS_OK = 0,
   CUTCELL_STATUS_INSUFFICIENT_ROWS = 1, /* fewer rows than monomials (N < M)            */
-  CUTCELL_STATUS_RANK_DEFICIENT = 2,    /* min L_kk <= 1e-7 max L_kk for the Cholesky
-                                           factor of the column-equilibrated W A       */
+  CUTCELL_STATUS_RANK_DEFICIENT = 2,    /* min |R_kk| <= 1e-12 max |R_kk| for the
+                                           Householder R factor of the column-
+                                           equilibrated W A                             */
   CUTCELL_STATUS_NONFINITE = 3          /* a non-finite moment or weight in the system  */
 };
 
@@ -153,9 +154,23 @@ typedef struct {
                            (Sec. 2.4); 1: W = (2d)^-weight_power instead (weight studies;
                            0 gives unweighted least squares)                            */
   double weight_power;  /* used when weight_custom = 1; in [0, 16]                      */
+  int32_t factorization; /* how the least-squares systems are solved (Sec. 2.2.1, eq.
+                           'stencil equation solution'; the stencil is the same either
+                           way, to the tolerance below):
+                           CUTCELL_FACTOR_AUTO: the Gram matrix of the column-equilibrated
+                             W A (matrix cores), inverted, with two steps of refinement;
+                             a face whose smallest pivot is at most 1e-4 of the largest,
+                             or whose refinement has not settled to 2^-40 of the stencil,
+                             is solved again by the QR path;
+                           CUTCELL_FACTOR_QR: every face by the QR path -- Householder QR
+                             of W A held in shared memory, with the rows and the
+                             refinement residuals of the augmented system in
+                             double-double arithmetic, so the stencil is correct to FP64
+                             rounding while cond(W A) * eps < 1.                        */
 } cutcell_opts;
 
 enum { CUTCELL_BC_DIRICHLET = 0, CUTCELL_BC_NEUMANN = 1 };
+enum { CUTCELL_FACTOR_AUTO = 0, CUTCELL_FACTOR_QR = 1 };
 
 /* One geometry: device arrays in the layouts above. */
 typedef struct {
@@ -383,6 +398,10 @@ int cutcell_last_profile(double* ms, int32_t n);
 /* Faces whose stencil the last build on the calling thread copied from a template
  * (cutcell_opts.reuse_templates), 0 without reuse. */
 int64_t cutcell_last_reused_faces(void);
+
+/* Faces of the last build on the calling thread that the Householder QR path solved
+ * (all of them under CUTCELL_FACTOR_QR). */
+int64_t cutcell_last_qr_faces(void);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* cutcell_last_error(void);

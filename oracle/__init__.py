@@ -18,6 +18,7 @@ from .stencils import (  # noqa: F401
     Enumeration,
     enumerate_geometry,
     neighbours,
+    neighbours_all,
     face_system,
     face_stencil,
     face_condition,

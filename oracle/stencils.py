@@ -284,6 +284,37 @@ def neighbours(en: Enumeration, f: int, R: int) -> np.ndarray:
     return np.asarray(idx, dtype=np.int64)
 
 
+def neighbours_all(en: Enumeration, R: int):
+    """The rows of every flux face at once, as CSR (row_ptr, col), the same sets as
+    neighbours() face by face (Sec. 2.4; readings R1, R2), from sparse matrices: with A the
+    adjacency of volumes through grid faces of positive area, the volumes within path
+    distance R of volume v are the nonzero pattern of row v of (I + A)^R; a face's volumes
+    are the union over its adjacent volumes; its EB and box rows are those of the volumes
+    in that union.  Columns ascending: volumes, EB faces, box faces."""
+    import scipy.sparse as sp
+
+    nv, nf = en.n_vol, en.n_face
+    grid = en.face_kind == KIND_GRID
+    lo, hi = en.face_lo[grid], en.face_hi[grid]
+    A = sp.csr_matrix((np.ones(2 * len(lo)), (np.concatenate([lo, hi]), np.concatenate([hi, lo]))), shape=(nv, nv))
+    step = (sp.identity(nv, format="csr") + A).tocsr()
+    step.data[:] = 1.0
+    reach = sp.identity(nv, format="csr")
+    for _ in range(R):
+        reach = (reach @ step).tocsr()
+        reach.data[:] = 1.0
+    has_lo, has_hi = en.face_lo >= 0, en.face_hi >= 0
+    rows = np.concatenate([np.flatnonzero(has_lo), np.flatnonzero(has_hi)])
+    cols = np.concatenate([en.face_lo[has_lo], en.face_hi[has_hi]])
+    adj = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(nf, nv))
+    fv = (adj @ reach).tocsr()
+    ve = sp.csr_matrix((np.ones(en.n_eb), (en.vol_of_cell[en.eb_cell], np.arange(en.n_eb))), shape=(nv, en.n_eb))
+    vb = sp.csr_matrix((np.ones(en.n_box), (en.vol_of_cell[en.box_cell], np.arange(en.n_box))), shape=(nv, en.n_box))
+    full = sp.hstack([fv, fv @ ve, fv @ vb], format="csr")
+    full.sort_indices()
+    return full.indptr.astype(np.int64), full.indices.astype(np.int64)
+
+
 # ---------------------------------------------------------------------------------
 # Sec. 2.2.1: rows of A, the weights and the flux vector
 

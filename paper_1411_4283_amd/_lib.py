@@ -30,11 +30,14 @@ class Opts(ctypes.Structure):
         ("reuse_templates", ctypes.c_int32),
         ("weight_custom", ctypes.c_int32),
         ("weight_power", ctypes.c_double),
+        ("factorization", ctypes.c_int32),
     ]
 
 
 BC_DIRICHLET = 0
 BC_NEUMANN = 1
+FACTOR_AUTO = 0
+FACTOR_QR = 1
 
 
 class Geom(ctypes.Structure):
@@ -159,6 +162,7 @@ SIGNATURES = {
     "cutcell_set_profiling": (None, [ctypes.c_int]),
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "cutcell_last_reused_faces": (ctypes.c_int64, []),
+    "cutcell_last_qr_faces": (ctypes.c_int64, []),
     "cutcell_last_error": (ctypes.c_char_p, []),
     "cutcell_abi_version": (ctypes.c_int, []),
 }

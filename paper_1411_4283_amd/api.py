@@ -70,14 +70,23 @@ class DeviceGeometry:
 _BC = {"dirichlet": _lib.BC_DIRICHLET, "neumann": _lib.BC_NEUMANN}
 
 
+_FACTOR = {"auto": _lib.FACTOR_AUTO, "qr": _lib.FACTOR_QR}
+
+
 def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = "dirichlet",
-              reuse_templates: bool = False, weight_power: float | None = None) -> Opts:
+              reuse_templates: bool = False, weight_power: float | None = None,
+              factorization: str = "auto") -> Opts:
     """cutcell_opts; eb_bc: "dirichlet" or "neumann" on every embedded-boundary face;
     reuse_templates: copy the stencils of faces whose systems are bitwise identical;
-    weight_power: the exponent p of W = (2d)^-p (None: the paper's 5)."""
+    weight_power: the exponent p of W = (2d)^-p (None: the paper's 5);
+    factorization: "auto" (Gram path, ill-conditioned faces by Householder QR) or "qr"
+    (every face by Householder QR)."""
     if eb_bc not in _BC:
         raise ValueError(f"eb_bc must be one of {sorted(_BC)}")
+    if factorization not in _FACTOR:
+        raise ValueError(f"factorization must be one of {sorted(_FACTOR)}")
     o = Opts()
+    o.factorization = _FACTOR[factorization]
     o.eb_bc = _BC[eb_bc]
     o.reuse_templates = 1 if reuse_templates else 0
     o.weight_custom = 0 if weight_power is None else 1
@@ -109,6 +118,7 @@ class Stencils:
     face_off: torch.Tensor
     code: int = 0
     reused: int = 0            # faces whose stencil was copied from a template
+    qr_faces: int = 0          # faces the Householder QR path solved
     transpose: "Transpose | None" = None
     _keep: list = field(default_factory=list, repr=False)
 
@@ -196,14 +206,15 @@ class Builder:
     grid, order and path radius, so repeated builds allocate nothing new."""
 
     def __init__(self, geoms, path_radius: int, device="cuda", eb_bc: str = "dirichlet",
-                 reuse_templates: bool = False, weight_power: float | None = None):
+                 reuse_templates: bool = False, weight_power: float | None = None, factorization: str = "auto"):
         geoms = list(geoms) if isinstance(geoms, (list, tuple)) else [geoms]
         g0 = geoms[0]
         for g in geoms:
             assert (g.dim, g.n, g.h, g.order) == (g0.dim, g0.n, g0.h, g0.order), "a batch shares its grid"
         self.geoms = geoms
         self.dim = g0.dim
-        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc, reuse_templates, weight_power)
+        self.opts = make_opts(g0.dim, g0.n, g0.h, g0.order, path_radius, eb_bc, reuse_templates, weight_power,
+                              factorization)
         self.eb_bc = eb_bc
         self.garr = (Geom * len(geoms))(*[g.struct() for g in geoms])
         lib = load()
@@ -271,6 +282,7 @@ class Builder:
                                            self.workspace.numel(), _stream(stream))
         out.code = check(rc, "cutcell_build_stencils")
         out.reused = int(load().cutcell_last_reused_faces())
+        out.qr_faces = int(load().cutcell_last_qr_faces())
         return out
 
 

@@ -17,13 +17,14 @@ constexpr int kPhases = 6;   // enumerate, count+scan, fill, bin, solve, tables
 static thread_local bool g_profiling = false;
 static thread_local double g_phase_ms[kPhases] = {-1, -1, -1, -1, -1, -1};
 static thread_local int64_t g_last_reused = 0;
+static thread_local int64_t g_last_qr = 0;
 
 struct PhaseTimer {
   hipEvent_t ev[kPhases + 1];
   int n = 0;
   bool on;
   hipStream_t st;
-  PhaseTimer(hipStream_t s) : on(g_profiling), st(s) {
+  PhaseTimer(hipStream_t s, bool allowed = true) : on(g_profiling && allowed), st(s) {
     if (!on) return;
     for (int i = 0; i <= kPhases; ++i)
       if (hipEventCreate(&ev[i]) != hipSuccess) on = false;
@@ -101,6 +102,8 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   t.perm = (int32_t*)take(sizeof(int32_t) * totface);
   t.bins = (int32_t*)take(sizeof(int32_t) * kBinWords);
   t.flagged = (int32_t*)take(sizeof(int32_t) * 2);
+  t.qr_count = (int32_t*)take(sizeof(int32_t));
+  t.qr_list = (int32_t*)take(sizeof(int32_t) * totface);
   t.geoms = (GeomPtrs*)take(sizeof(GeomPtrs) * G);
   t.bytes = off;
   if (w) *w = t;
@@ -119,6 +122,8 @@ static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
     return fail(CUTCELL_E_INVALID_ARG, "weight_power must be in [0, 16]");
   if (o->reuse_templates != 0 && o->reuse_templates != 1)
     return fail(CUTCELL_E_INVALID_ARG, "reuse_templates must be 0 or 1");
+  if (o->factorization != CUTCELL_FACTOR_AUTO && o->factorization != CUTCELL_FACTOR_QR)
+    return fail(CUTCELL_E_INVALID_ARG, "factorization must be CUTCELL_FACTOR_AUTO or CUTCELL_FACTOR_QR");
   if (o->eb_bc != CUTCELL_BC_DIRICHLET && o->eb_bc != CUTCELL_BC_NEUMANN)
     return fail(CUTCELL_E_INVALID_ARG, "eb_bc must be CUTCELL_BC_DIRICHLET or CUTCELL_BC_NEUMANN");
   if (o->tuning)
@@ -316,13 +321,14 @@ int cutcell_query(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts*
 
 static int build_common(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
                         const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
-                        cutcell_stream_t stream, cutcell_tuning* tune_out, int reps, double* best_ms) {
+                        cutcell_stream_t stream, cutcell_tuning* tune_out, int reps, double* best_ms,
+                        bool timing_allowed = true) {
   if (!sizes || !out) return fail(CUTCELL_E_INVALID_ARG, "sizes/out is NULL");
   if (!out->row_ptr || !out->col || !out->val || !out->status || !out->vol_face || !out->vol_scale ||
       !out->phi_off || !out->vol_off || !out->face_off)
     return fail(CUTCELL_E_INVALID_ARG, "an output array is NULL");
   hipStream_t st = (hipStream_t)stream;
-  PhaseTimer timer(st);
+  PhaseTimer timer(st, timing_allowed);
   timer.mark();
   Prepared P;
   int rc = prepare(geoms, n_geom, opts, workspace, workspace_bytes, st, &P);
@@ -372,10 +378,12 @@ static int build_common(const cutcell_geom* geoms, int32_t n_geom, const cutcell
   CC_HIP(hipMemcpyAsync(out->phi_off, w.offs, ob, hipMemcpyDeviceToDevice, st));
   CC_HIP(hipMemcpyAsync(out->vol_off, w.offs + (n_geom + 1), ob, hipMemcpyDeviceToDevice, st));
   CC_HIP(hipMemcpyAsync(out->face_off, w.offs + 2 * (n_geom + 1), ob, hipMemcpyDeviceToDevice, st));
-  int32_t flagged = 0;
+  int32_t flagged = 0, nqr = 0;
   CC_HIP(hipMemcpyAsync(&flagged, w.flagged, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CC_HIP(hipMemcpyAsync(&nqr, w.qr_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   CC_HIP(hipGetLastError());
+  g_last_qr = nqr;
   timer.finish();
   return flagged ? CUTCELL_W_FLAGGED_FACES : CUTCELL_OK;
 }
@@ -400,6 +408,8 @@ int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_op
 void cutcell_set_profiling(int enable) { g_profiling = enable != 0; }
 
 int64_t cutcell_last_reused_faces(void) { return g_last_reused; }
+
+int64_t cutcell_last_qr_faces(void) { return g_last_qr; }
 
 int cutcell_last_profile(double* ms, int32_t n) {
   if (!ms || n < 0) return fail(CUTCELL_E_INVALID_ARG, "ms is NULL");
@@ -641,6 +651,7 @@ int cutcell_stencils_backward(const cutcell_geom* geoms, int32_t n_geom, const c
   ba.weight_bar = weight_bar;
   ba.owner_grad = b.owner_grad;
   ba.grads = b.grads;
+  ba.fwd_status = st_->status;
   rc = backward_stencils(w, *opts, bc, st_->row_ptr, st_->col, ba, st);
   if (rc) return rc;
   ReduceArgs R{};

@@ -53,7 +53,9 @@ struct Work {
   int64_t* rp_tmp;      // [G*maxface + 1] row offsets when the caller has none (query)
   int32_t* perm;        // [G*maxface]
   int32_t* bins;        // [kBinWords] bucket counts, bucket cursors, max rows, part counts
-  int32_t* flagged;     // [1]
+  int32_t* flagged;     // [2] flagged faces, bad EB input
+  int32_t* qr_count;    // [1] faces left to the Householder QR path
+  int32_t* qr_list;     // [G*maxface] those faces
   GeomPtrs* geoms;      // [G]
   size_t bytes;
 };
@@ -78,6 +80,7 @@ struct BackwardArgs {
   double* owner_grad;           // [n_face][4]      EB faces: d/d vol_mom[owner][0..D]; 0 otherwise
   const GradPtrs* grads;        // [G]  the face-moment and EB normal-moment gradients are
                                 //      written here directly (Fbar)
+  const int8_t* fwd_status;     // [n_face] status of the forward build
 };
 
 // Transposed (CSC) structure of the stencils: the nonzeros of each Phi entry in
@@ -144,6 +147,11 @@ struct ReduceArgs {
   const double* scale_bar;    // [n_vol] or null
 };
 
+// the Householder QR path (stencil_qr.hip): faces list[0 .. n), n = *count_dev if given,
+// else count_host
+int solve_qr_faces(const Work& w, const cutcell_opts& o, const int32_t* list, const int32_t* count_dev,
+                   long long count_host, const int64_t* row_ptr, const int32_t* col, double* val, int8_t* status,
+                   hipStream_t st);
 int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
                   const int32_t* col, double* val, int8_t* status, hipStream_t st, cutcell_tuning* out, int reps,
                   double* best_ms);

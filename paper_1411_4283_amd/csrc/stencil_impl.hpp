@@ -6,35 +6,75 @@
 // wavefront owns one face:
 //   1. rows: each lane builds its row(s) of B in registers -- the row's moments,
 //      re-centred to x0 by the binomial theorem, divided by the zeroth moment and
-//      scaled by the weight -- and stores them in LDS;
+//      scaled by the weight -- and stores them in LDS; a row whose zeroth moment is
+//      below kSmallCell is formed in double-double and rounded (the moments of a small
+//      cut cell about its centre nearly cancel when shifted to x0);
 //   2. G = B^T B on the FP64 matrix cores (v_mfma_f64_16x16x4f64, 16 x 16 tiles, rows
 //      of B as the contraction index); lane i collects row i from the tiles with
 //      ds_bpermute (no shared-memory copy of G);
 //   3. G is equilibrated to unit diagonal and inverted by symmetric Gauss-Jordan sweeps,
 //      lane i holding row i in registers; the sweep pivots are the Cholesky pivots;
-//   4. z from the semi-normal equations z = B G^-1 F~ followed by two steps of
-//      refinement with the residual F~ - B^T z computed from B itself, which brings the
-//      error down to that of a backward-stable solve (cond(B) * eps);
+//   4. z from the semi-normal equations z = B G^-1 F~ followed by one step of refinement
+//      with the residual F~ - B^T z computed from B itself in compensated arithmetic
+//      (twice the working precision), which leaves the error of rounding B to FP64, a few
+//      1e-17 cond(B), where the initial error is ~cond(B)^2 eps;
 //   5. val = h^(D-2) W z.
 // Under Neumann EB conditions (a separate kernel instance) the EB rows are the
 // normal-derivative rows of eq. 'Neu moment eq for cp' and their values carry h^(D-1);
 // the EB faces themselves have a one-entry stencil (their area) and are written by
 // k_insufficient, the kernel of faces with fewer rows than monomials.
-// Status: fewer rows than monomials, a pivot square root below 1e-7 times the largest after
-// equilibration (numerically rank deficient), or a non-finite entry flag the face.
+// Status: fewer rows than monomials or a non-finite entry flag the face.  A face is left to
+// the Householder QR path (stencil_qr.hpp), which also decides rank deficiency, when
+//   * its condition bound sqrt(||G^||_inf ||G^^-1||_F) (>= cond_2 of the equilibrated B,
+//     and within 1.35x of it on the workloads) exceeds kCondRoute: with the rows of small
+//     cells formed in double-double (below) the stencil is good to about 1.5e-16 cond,
+//     which must stay below the 1e-11 it is held to;
+//   * its smallest pivot square root is at most kRouteTol times the largest; or
+//   * its refinement step moved the stencil by more than kSettleTol of its size (the error
+//     left after the step is about the square of that fraction).
 #pragma once
 
 #include <algorithm>
 
 #include "kernels.hpp"
 #include "rows.hpp"
+#include "rows_dd.hpp"
 
 namespace cutcell {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr double kRankTol = 1e-7;
-constexpr int kRefine = 2;
+constexpr double kRouteTol = 1e-4;
+constexpr double kCondRoute = 3e4;
+constexpr double kSmallCell = 1e-3;      // rows (and EB flux vectors) of smaller cells in double-double
+constexpr double kSettleTol = 1e-6;
+constexpr int kRefine = 1;
+constexpr int kRefineBackward = 2;   // refinement steps of the adjoint's least-squares solve
+constexpr int kStatusRoute = 100;        // internal: the face goes to the QR path
+
+// Compensated dot product (Ogita, Rump and Oishi, SIAM J. Sci. Comput. 26(6), 2005,
+// algorithm Dot2): s + c holds the running sum as if it were carried in twice the working
+// precision.  The product's rounding error comes from the FMA, the sum's from TwoSum.
+struct Dot2 {
+  double s, c;
+};
+__device__ __forceinline__ void dot2_add(Dot2& a, double x, double y) {
+#pragma clang fp contract(off)
+  const double p = x * y;
+  const double e = __builtin_fma(x, y, -p);
+  const double s = a.s + p;
+  const double bb = s - a.s;
+  const double q = (a.s - (s - bb)) + (p - bb);
+  a.s = s;
+  a.c += q + e;
+}
+__device__ __forceinline__ double dot2_merge(Dot2 a, Dot2 b) {
+#pragma clang fp contract(off)
+  const double s = a.s + b.s;
+  const double bb = s - a.s;
+  const double q = (a.s - (s - bb)) + (b.s - bb);
+  return s + ((a.c + b.c) + q);
+}
 
 // 1/d from v_rcp_f64 and two Newton steps (each squares the relative error)
 __device__ __forceinline__ double recip_f64(double d) {
@@ -197,11 +237,25 @@ __device__ __forceinline__ void face_x0(const GridDims& g, const GeomPtrs& gp, F
   }
 }
 
+// x0 / h in double-double: exact for grid and box faces; for an EB face the cut cell's
+// centre plus its first moments over its zeroth moment (face_x0 must have run).
+template <int D, int Q>
+__device__ __forceinline__ void face_x0_dd(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi, dd* x0) {
+  constexpr int M = Dims<D, Q>::M;
+  for (int ax = 0; ax < 3; ++ax) x0[ax] = dd_from(fi.x0h[ax]);
+  if (fi.kind == 0) return;
+  const int32_t c = fi.owner_cell;
+  const int cown[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+  const double* vm = gp.vol_mom + (long long)c * M;
+  const dd k0 = dd_from(vm[0]);
+  for (int ax = 0; ax < D; ++ax) x0[ax] = dd_add(dd_from(cown[ax] + 0.5), dd_div(dd_from(vm[1 + ax]), k0));
+}
+
 // Entry `lane` of the flux vector F~ (0 for lanes >= M) and, for EB faces, the normal
 // moments re-centred to x0 (sm.nus, lanes 0..D-1 one component each).  Ends with a barrier.
 template <int D, int Q, class SM>
 __device__ __forceinline__ double face_flux(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi, SM& sm,
-                                            int lane) {
+                                            int lane, const dd* x0dd) {
   constexpr int M = Dims<D, Q>::M, Mf = Dims<D, Q>::Mf, M1 = Dims<D, Q>::M1;
   const int dn = fi.dn;
   double fv = 0.0;
@@ -224,13 +278,24 @@ __device__ __forceinline__ double face_flux(const GridDims& g, const GeomPtrs& g
     __syncthreads();
     return fv;
   }
-  if (lane < D) {
+  const bool small = gp.vol_mom[(long long)fi.owner_cell * M] < kSmallCell;
+  if (lane < D && !small) {
     double nu[M1];
     const double* src = gp.eb_nmom + ((long long)fi.ref * D + lane) * M1;
     static_for<0, M1>([&](auto I) { nu[I] = src[I]; });
     double dl[3] = {-fi.off[0], -fi.off[1], -fi.off[2]};   // (c - x0)/h
     recentre<D, Q - 1>(nu, dl);
     static_for<0, M1>([&](auto I) { sm.nus[lane][I] = nu[I]; });
+  } else if (lane < D) {   // a small cut cell: the shift to its centroid in double-double
+    dd nu[M1];
+    const double* src = gp.eb_nmom + ((long long)fi.ref * D + lane) * M1;
+    static_for<0, M1>([&](auto I) { nu[I] = dd_from(src[I]); });
+    const int32_t c = fi.owner_cell;
+    const int cown[3] = {(int)(c % g.n[0]), (int)((c / g.n[0]) % g.n[1]), (int)(c / ((long long)g.n[0] * g.n[1]))};
+    dd dl[3] = {dd_from(0.0), dd_from(0.0), dd_from(0.0)};
+    for (int ax = 0; ax < D; ++ax) dl[ax] = dd_sub(dd_from(cown[ax] + 0.5), x0dd[ax]);   // (c - x0)/h
+    recentre_dd<D, Q - 1>(nu, dl);
+    static_for<0, M1>([&](auto I) { sm.nus[lane][I] = nu[I].hi + nu[I].lo; });
   }
   __syncthreads();
   if (lane < M) {
@@ -251,7 +316,7 @@ __device__ __forceinline__ double face_flux(const GridDims& g, const GeomPtrs& g
 // Rows, Gram matrix, inverse and the refined semi-normal solve of one face.  Leaves B in
 // shared memory, -G^^-1 (row `lane`) in a[], the column equilibration in sdiag, and W and
 // z of rows lane, lane + 64, ... in wreg[], zreg[]; the adjoint's layout (SM::kFull) also
-// keeps W, z and y in shared memory.  Returns the face status.
+// keeps W, z and y in shared memory.  Returns the face status, or kStatusRoute.
 template <int D, int Q, int NPAD, bool NEU, class SM>
 __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
                                             const int32_t* __restrict__ vol_cell, const int32_t* __restrict__ box_lf,
@@ -267,6 +332,8 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   // issued before the first row is finished, so the dependent loads of all rows overlap.
   constexpr int NR = (NPAD + 63) / 64;
   bool finite = true;
+  dd x0dd[3];
+  face_x0_dd<D, Q>(g, gp, fi, x0dd);
   RowSource rsrc[NR];
   static_for<0, NR>([&](auto R) {
     const int r = lane + 64 * R;
@@ -280,13 +347,14 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       double m[M];
       double wr = 0.0;
       if (r < N) {
-        if constexpr (NEU) {
-          if (rsrc[R].eb >= 0) {
-            finite = neumann_row<D, Q>(gp, rsrc[R].eb, rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
-          } else {
-            load_row_moments<D, Q>(rsrc[R], m);
-            finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
-          }
+        const bool neu_row = NEU && rsrc[R].eb >= 0;
+        const double m0 = neu_row ? gp.eb_mom[(long long)rsrc[R].eb * M] : rsrc[R].src[0];
+        if (!(m0 >= kSmallCell)) {   // a small cell (or a non-finite moment): double-double
+          dd md[M];
+          finite = dd_row<D, Q, NEU>(gp, rsrc[R], x0dd, wpow, md, wr) && finite;
+          static_for<0, M>([&](auto I) { m[I] = md[I].hi; });
+        } else if (neu_row) {
+          finite = neumann_row<D, Q>(gp, rsrc[R].eb, rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
         } else {
           load_row_moments<D, Q>(rsrc[R], m);
           finite = finish_row<D, Q>(rsrc[R].ctr, fi.x0h, m, wr, wpow) && finite;
@@ -299,7 +367,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       if constexpr (SM::kFull) sm.wls[r] = wr;
     }
   });
-  const double fv = face_flux<D, Q>(g, gp, fi, sm, lane);   // barrier: B complete
+  const double fv = face_flux<D, Q>(g, gp, fi, sm, lane, x0dd);   // barrier: B complete
   const bool allfinite = __all(finite) && __all(isfinite(fv));
 
   // ---- G = B^T B: full 16-column tiles on the matrix cores --------------------------------
@@ -387,6 +455,8 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   static_for<0, M>([&](auto C) { gdiag = (lane == C) ? a[C] : gdiag; });
   sdiag = act ? 1.0 / sqrt(gdiag) : 1.0;
   static_for<0, M>([&](auto J) { a[J] = act ? a[J] * sdiag * readlane_f64(sdiag, J) : 0.0; });
+  double gnorm = 0.0;   // ||G^||_inf: largest absolute row sum of the equilibrated Gram matrix
+  static_for<0, M>([&](auto J) { gnorm += fabs(a[J]); });
   double pmax = 0.0, pmin = 1e300;
   // Step k:  a_ij -= (a_ik / d) a_kj  (i, j != k);  a_ik /= d;  a_kj /= d;  a_kk = -1/d.
   // Each lane scales its multiplier once (u = a_ik / d; on lane k, 1 - 1/d turns the
@@ -414,16 +484,21 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     });
     a[k] = (lane == k) ? -rd : u;
   });
-  const bool rankok = (pmin > kRankTol * pmax) && (pmax > 0.0);
-  int st = CUTCELL_STATUS_OK;
-  if (!allfinite) st = CUTCELL_STATUS_NONFINITE;
-  else if (!rankok) st = CUTCELL_STATUS_RANK_DEFICIENT;
+  const bool pivots_ok = (pmin > kRouteTol * pmax) && (pmax > 0.0);
+  double inv2 = 0.0;    // ||G^^-1||_F^2, from the rows of the inverse
+  static_for<0, M>([&](auto J) { inv2 = fma(a[J], a[J], inv2); });
+  for (int o = 32; o > 0; o >>= 1) {
+    gnorm = fmax(gnorm, __shfl_xor(gnorm, o));
+    inv2 += __shfl_xor(inv2, o);
+  }
+  const bool cond_ok = gnorm * sqrt(inv2) <= kCondRoute * kCondRoute;
 
-  // ---- semi-normal solve with refinement ----------------------------------------------------
+  // ---- semi-normal solve with one compensated refinement step ---------------------------------
   // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs).  Lane p holds
   // component p of F~, rhs and y; lane r holds z of its rows r, r + 64.
   double rhs = fv * sdiag;
   double ysum = 0.0;
+  double dlast = 0.0;   // largest change of W z in the refinement step
   static_for<0, NR>([&](auto R) { zreg[R] = 0.0; });
   for (int it = 0; it <= kRefine; ++it) {
     double tq[4] = {0.0, 0.0, 0.0, 0.0};
@@ -437,11 +512,14 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       if (r < NPAD) {
         double sq4[4] = {0.0, 0.0, 0.0, 0.0};
         static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], readlane_f64(dy, J), sq4[J % 4]); });
-        zreg[R] += (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
+        const double inc = (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
+        zreg[R] += inc;
+        if (it == kRefine) dlast = fmax(dlast, fabs(wreg[R] * inc));
       }
     });
     if (it == kRefine) break;
-    // residual of B^T z = F~, equilibrated; z goes through LDS, B^T is read by columns
+    // residual of B^T z = F~ in compensated arithmetic (two interleaved Dot2 sums); z goes
+    // through LDS, B^T is read by columns
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
       if (r < NPAD) sm.zs[r] = zreg[R];
@@ -449,15 +527,13 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     __syncthreads();
     double res = 0.0;
     if (act) {
-      double r0 = fv, r1 = 0.0, r2 = 0.0, r3 = 0.0;
+      Dot2 d0{fv, 0.0}, d1{0.0, 0.0};
 #pragma unroll 4
-      for (int r = 0; r < NPAD; r += 4) {
-        r0 = fma(-Bs[(r + 0) * MS + lane], sm.zs[r + 0], r0);
-        r1 = fma(-Bs[(r + 1) * MS + lane], sm.zs[r + 1], r1);
-        r2 = fma(-Bs[(r + 2) * MS + lane], sm.zs[r + 2], r2);
-        r3 = fma(-Bs[(r + 3) * MS + lane], sm.zs[r + 3], r3);
+      for (int r = 0; r < NPAD; r += 2) {
+        dot2_add(d0, -Bs[(r + 0) * MS + lane], sm.zs[r + 0]);
+        dot2_add(d1, -Bs[(r + 1) * MS + lane], sm.zs[r + 1]);
       }
-      res = (r0 + r1) + (r2 + r3);
+      res = dot2_merge(d0, d1);
     }
     rhs = res * sdiag;
     __syncthreads();
@@ -470,7 +546,17 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     if (act) sm.ys[lane] = ysum;
     __syncthreads();
   }
-  return st;
+  // has the refinement settled?  The step's change of the stencil W z against its size
+  double smax = 0.0;
+  static_for<0, NR>([&](auto R) { smax = fmax(smax, fabs(wreg[R] * zreg[R])); });
+  for (int o = 32; o > 0; o >>= 1) {
+    dlast = fmax(dlast, __shfl_xor(dlast, o));
+    smax = fmax(smax, __shfl_xor(smax, o));
+  }
+  const bool settled = dlast <= kSettleTol * smax;
+  if (!allfinite) return CUTCELL_STATUS_NONFINITE;
+  if (!pivots_ok || !cond_ok || !settled) return kStatusRoute;
+  return CUTCELL_STATUS_OK;
 }
 
 struct StencilArgs {
@@ -494,6 +580,8 @@ struct StencilArgs {
   int per_xcd;
   double h;            // grid spacing (Neumann rows carry one more power of h)
   double wpow;         // weight exponent p of W = (2 |delta|)^-p
+  int32_t* qr_list;    // faces left to the Householder QR path, and their count
+  int32_t* qr_count;
 };
 
 // Faces of a bin taken by workgroup blockIdx.x in turn (-1 when done).  With xcd = 1 and a
@@ -547,6 +635,10 @@ __device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, 
   const int st = face_forward<D, Q, NPAD, NEU>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
                                                A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a,
                                                sdiag, wreg, zreg, A.wpow);
+  if (st == kStatusRoute) {   // the QR path writes this face's values and status
+    if (lane == 0) A.qr_list[atomicAdd(A.qr_count, 1)] = fi.F;
+    return;
+  }
   static_for<0, NR>([&](auto R) {
     const int r = lane + 64 * R;
     if (r < fi.N) {
@@ -635,7 +727,9 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
   const int st = face_forward<D, Q, NPAD, false>(A.g, gp, fi, vol_cell, box_lf, A.col, sm, lane, a, sdiag, wreg, zreg,
                                                  A.wpow);
   const double* Bs = sm.Bs;
-  if (st != CUTCELL_STATUS_OK) {   // a flagged face has s = 0 whatever its inputs: no gradient
+  // a flagged face has s = 0 whatever its inputs: no gradient (the forward status decides
+  // for the faces the forward build solved by Householder QR)
+  if (st == CUTCELL_STATUS_NONFINITE || B.fwd_status[fi.F] != CUTCELL_STATUS_OK) {
     for (int r = lane; r < N; r += 64) {
       B.nz_rz[2 * (fi.rp + r)] = 0.0;
       B.nz_rz[2 * (fi.rp + r) + 1] = 0.0;
@@ -654,7 +748,7 @@ __global__ __launch_bounds__(64) void k_stencil_backward(StencilArgs A, Backward
   // w = G^-1 B^T zbar, refined:  w += G^-1 B^T (zbar - B w); lane p holds w_p
   constexpr int NR = (NPAD + 63) / 64;
   double wl = 0.0;
-  for (int it = 0; it <= kRefine; ++it) {
+  for (int it = 0; it <= kRefineBackward; ++it) {
     double res = 0.0;
     if (act) {
       double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
@@ -825,6 +919,8 @@ inline StencilArgs stencil_args(const Work& w, double hscale, const int32_t* per
   A.col = col;
   A.h = 0.0;
   A.wpow = 5.0;
+  A.qr_list = w.qr_list;
+  A.qr_count = w.qr_count;
   return A;
 }
 

@@ -30,7 +30,7 @@ def test_header_declares_the_entry_points():
               "cutcell_last_error", "cutcell_abi_version", "cutcell_stencils_backward", "cutcell_apply_adjoint",
               "cutcell_build_transpose", "cutcell_transpose_workspace_bytes", "cutcell_backward_workspace_bytes",
               "cutcell_solve", "cutcell_solve_workspace_bytes", "cutcell_laplacian_count", "cutcell_laplacian_fill",
-              "cutcell_apply_laplacian", "cutcell_laplacian_workspace_bytes", "cutcell_last_reused_faces",
+              "cutcell_apply_laplacian", "cutcell_laplacian_workspace_bytes", "cutcell_last_reused_faces", "cutcell_last_qr_faces",
               "cutcell_ritz", "cutcell_ritz_workspace_bytes", "cutcell_hessenberg_eigs"):
         assert n in names
 
@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 10
+    assert lib.cutcell_abi_version() == 11
 
 
 def _opts(**kw):

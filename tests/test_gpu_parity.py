@@ -2,10 +2,9 @@
 
 Bars (written in each test):
   * row_ptr, col and status bit-exact;
-  * stencil values per face: max|s_gpu - s_orc| <= tol * max|s_orc|, tol = 1e-11 for faces
-    whose column-equilibrated W A has cond <= 1e5, tol = 1e-11 * cond / 1e5 above (both
-    sides are backward-stable solves with forward error ~ cond * eps; measured
-    differences stay below 6e-17 * cond);
+  * stencil values per face: max|s_gpu - s_orc| <= 1e-11 * max|s_orc| (flat: the oracle
+    computes in extended precision, its own error stays below 1e-12 up to cond ~1e7, and
+    faces the Gram path cannot resolve to this bar are solved by Householder QR);
   * L(Phi) on the same stencils: per volume |dL_v| <= 1e-12 * sum_f sum_j |s_fj Phi_j| / |V_v|
     and ||dL||_2 <= 1e-12 ||L||_2.
 Small cases are compared entry by entry; the full-size 64^3 workload on sampled faces
@@ -59,9 +58,7 @@ def _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g):
             assert np.all(val_g[a:b] == 0)
             continue
         err = np.abs(val_g[a:b] - s).max() / np.abs(s).max()
-        if err > 1e-11:
-            cond = oracle.face_condition(g, en, f, R)
-            assert err <= 1e-11 * cond / 1e5, f"face {f}: rel err {err:.3e}, cond {cond:.3e}"
+        assert err <= 1e-11, f"face {f}: rel err {err:.3e}, cond {oracle.face_condition(g, en, f, R):.3e}"
         worst = max(worst, err)
     return worst
 
@@ -122,11 +119,9 @@ def test_full_parity(name):
             assert np.all(val_g[a:b] == 0)
             continue
         err = np.abs(val_g[a:b] - val[a:b]).max() / np.abs(val[a:b]).max()
-        if err > 1e-11:
-            cond = oracle.face_condition(g, en, f, R)
-            assert err <= 1e-11 * cond / 1e5, f"face {f}: rel err {err:.3e}, cond {cond:.3e}"
+        assert err <= 1e-11, f"face {f}: rel err {err:.3e}, cond {oracle.face_condition(g, en, f, R):.3e}"
         worst = max(worst, err)
-    _say(f"{name}: {en.n_face} faces, worst stencil rel err {worst:.2e}")
+    _say(f"{name}: {en.n_face} faces, worst stencil rel err {worst:.2e}, {st.qr_faces} by QR")
     phi = np.random.default_rng(5).standard_normal(en.n_phi)
     _check_apply(g, en, st, rp_g, col_g, val_g, phi)
 
@@ -153,6 +148,88 @@ def test_full_size_counts_and_sampled_faces(c3):
                             np.nonzero(en.face_kind == S.KIND_BOX)[0][::500], [0, en.n_face - 1]])
     worst = _check_faces(g, en, 3, faces, rp_g, col_g, val_g, st_g)
     _say(f"c3 sampled {len(faces)} faces, worst rel err {worst:.2e}")
+
+
+def _targeted_faces(g, en, R, rng, n_small=50, n_cond=50, n_cand=600, n_rand=100, n_cells=5):
+    """Faces where the solves are hardest: those of the n_small smallest cut cells (their
+    EB face and grid faces), the n_cond worst-conditioned among n_cand seeded candidates
+    next to the boundary (EB faces and faces of cut cells), every face of the n_cells
+    smallest cells, and n_rand random faces.  Returns (faces, cond of the candidates)."""
+    kap = g.kappa[en.vol_cell]
+    cut = np.zeros(en.n_vol, bool)
+    cut[en.vol_of_cell[en.eb_cell]] = True
+    order = np.argsort(np.where(cut, kap, np.inf))
+    lo, hi = en.face_lo, en.face_hi
+
+    def faces_of(vols):
+        m = np.isin(lo, vols) | np.isin(hi, vols)
+        return np.flatnonzero(m)
+
+    small = faces_of(order[:n_small])[: 2 * n_small]
+    cells = faces_of(order[:n_cells])
+    near = np.flatnonzero(((lo >= 0) & cut[np.maximum(lo, 0)]) | ((hi >= 0) & cut[np.maximum(hi, 0)]))
+    cand = rng.choice(near, min(n_cand, len(near)), replace=False)
+    conds = np.array([oracle.face_condition(g, en, int(f), R) for f in cand])
+    worst = cand[np.argsort(conds)[-n_cond:]]
+    rand = rng.choice(en.n_face, n_rand, replace=False)
+    return np.unique(np.concatenate([small, worst, cells, rand])), conds
+
+
+def test_full_size_targeted_faces(c3):
+    """The 50 smallest cut cells' faces, the 50 worst-conditioned of 600 faces next to the
+    boundary, every face of the 5 smallest cells and 100 random faces, at the flat bar."""
+    g, en, dg, b, st = c3
+    rp_g, col_g, val_g, st_g = _host(st)
+    faces, conds = _targeted_faces(g, en, 3, np.random.default_rng(12))
+    worst = _check_faces(g, en, 3, faces, rp_g, col_g, val_g, st_g)
+    _say(f"c3 targeted: {len(faces)} faces, cond of candidates up to {conds.max():.2e} (p99 "
+         f"{np.percentile(conds, 99):.2e}), worst rel err {worst:.2e}; {st.qr_faces} faces by QR")
+
+
+def test_full_size_rows_bit_exact(c3):
+    """row_ptr and col of every face of the 64^3 workload equal the oracle's rows (Sec. 2.4),
+    computed for all faces at once by sparse reachability."""
+    g, en, dg, b, st = c3
+    rp, col = oracle.neighbours_all(en, 3)
+    rp_g = st.row_ptr.cpu().numpy()
+    assert np.array_equal(rp_g, rp)
+    assert np.array_equal(st.col[: st.sizes.nnz].cpu().numpy().astype(np.int64), col)
+    _say(f"c3 rows: {en.n_face} faces, {len(col)} entries bit-exact")
+
+
+def test_batched_perturbed_spheres_against_oracle():
+    """The batched workload (64 spheres at 48^3, centres 0.5 + U(-0.05,0.05)^3, radii
+    U(0.25,0.35), default_rng(3)): eight of its geometries (seeded choice) built as one batch,
+    and in each the faces of the 50 smallest cut cells, the 50 worst-conditioned of 400
+    boundary faces, every face of the 5 smallest cells and 100 random faces against the
+    oracle at the flat bar; row counts of every face of the batch against the oracle's."""
+    shapes = cg.perturbed_spheres(64, 3)
+    pick = sorted(np.random.default_rng(21).choice(64, 8, replace=False).tolist())
+    gs = [cg.make_geometry(shapes[i], 48, 4) for i in pick]
+    _say(f"c4 subset {pick}")
+    dgs = [cc.DeviceGeometry.from_host(g, DEV) for g in gs]
+    st = cc.Builder(dgs, 3).build()
+    torch.cuda.synchronize()
+    fo, po = st.face_off.cpu().numpy(), st.phi_off.cpu().numpy()
+    rpb = st.row_ptr.cpu().numpy()
+    colb = st.col[: st.sizes.nnz].cpu().numpy()
+    valb = st.val[: st.sizes.nnz].cpu().numpy()
+    stsb = st.status[: st.sizes.n_face].cpu().numpy()
+    worst_all, conds_all = 0.0, []
+    for k, g in enumerate(gs):
+        en = oracle.enumerate_geometry(g)
+        a, e = fo[k], fo[k + 1]
+        rp_g = rpb[a:e + 1] - rpb[a]
+        col_g = colb[rpb[a]:rpb[e]] - po[k]
+        val_g = valb[rpb[a]:rpb[e]]
+        rp_o, _ = oracle.neighbours_all(en, 3)
+        assert np.array_equal(rp_g, rp_o)
+        faces, conds = _targeted_faces(g, en, 3, np.random.default_rng(100 + k), n_cand=400)
+        worst_all = max(worst_all, _check_faces(g, en, 3, faces, rp_g, col_g, val_g, stsb[a:e]))
+        conds_all.append(conds)
+    c = np.concatenate(conds_all)
+    _say(f"c4: {len(gs)} geometries, {st.sizes.n_face} faces, {st.qr_faces} by QR; candidate cond p50 "
+         f"{np.median(c):.2e} p99 {np.percentile(c, 99):.2e} max {c.max():.2e}; worst rel err {worst_all:.2e}")
 
 
 def test_full_size_faces_of_every_row_count_in_the_split_bin(c3):
@@ -324,11 +401,9 @@ def test_star256_order4_full_size():
     rp_g, col_g, val_g, st_g = _host(st)
     _say(f"star256: {en.n_face} faces, nnz {len(col_g)}")
     assert st.sizes.n_face == en.n_face and st.sizes.n_phi == en.n_phi
-    nb = [oracle.neighbours(en, f, R) for f in range(en.n_face)]
-    rp = np.zeros(en.n_face + 1, np.int64)
-    rp[1:] = np.cumsum([len(x) for x in nb])
+    rp, col = oracle.neighbours_all(en, R)
     assert np.array_equal(rp_g, rp)
-    assert np.array_equal(col_g, np.concatenate(nb))
+    assert np.array_equal(col_g, col)
     eb_faces = np.flatnonzero(en.face_kind == S.KIND_EB)
     faces = np.unique(np.concatenate([eb_faces, np.random.default_rng(5).choice(en.n_face, 400, replace=False)]))
     worst = _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g)

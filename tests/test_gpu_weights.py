@@ -42,46 +42,25 @@ def _build(g, R, **kw):
     return dg, b, st
 
 
-def _exact_stencil(g, en, f, R, p):
-    """s = W^2 A (A^T W^2 A)^-1 F in 50-digit arithmetic from the same inputs."""
-    import mpmath
-
-    A, W, F, idx = oracle.face_system(g, en, f, R, wpow=p)
-    mpmath.mp.dps = 50
-    Am = mpmath.matrix(A.tolist())
-    W2 = mpmath.diag([mpmath.mpf(w) ** 2 for w in W])
-    y = mpmath.lu_solve(Am.T * W2 * Am, mpmath.matrix(F.tolist()))
-    return g.h ** (g.D - 2) * np.array([float(v) for v in W2 * Am * y])
-
-
 @pytest.mark.parametrize("p", [0.0, 3.0, 7.5])
 def test_weight_power_stencils_match_oracle(p):
-    """Bars as for p = 5.  Steep weights make some systems ill-conditioned; where the two
-    sides differ by more than the bar, the 50-digit solution decides: the GPU stencil must
-    be within the bar of it (the oracle's LAPACK solve then carries the difference: at
-    p = 7.5 it is off by 1.3 cond eps on a face of cond 9.3e5)."""
+    """Bars as for p = 5, flat: at p = 7.5 some systems reach cond 9.3e5; the oracle (extended
+    precision) stays within 1.4e-14 of 50-digit stencils there, and the GPU solves the faces
+    its Gram path cannot resolve by Householder QR."""
     g = cg.make_geometry(CIRCLE, 32, 4)
     dg, b, st = _build(g, 3, weight_power=p)
     en, rp, col, val, status = oracle.build(g, 3, wpow=p)
     rp_g, col_g, val_g, st_g = _host(st)
     assert np.array_equal(rp_g, rp) and np.array_equal(col_g, col) and np.array_equal(st_g, status)
-    worst, exact_checked = 0.0, 0
+    worst = 0.0
     for f in range(en.n_face):
         a, e = rp[f], rp[f + 1]
         if status[f] != oracle.STATUS_OK:
             continue
         err = np.abs(val_g[a:e] - val[a:e]).max() / np.abs(val[a:e]).max()
-        if err > 1e-11:
-            cond = oracle.face_condition(g, en, f, 3, wpow=p)
-            bar = 1e-11 * max(cond / 1e5, 1.0)
-            if err > bar:
-                se = _exact_stencil(g, en, f, 3, p)
-                eg = np.abs(val_g[a:e] - se).max() / np.abs(se).max()
-                assert eg <= bar, (f, eg, cond)
-                exact_checked += 1
-                err = eg
+        assert err <= 1e-11, (f, err, oracle.face_condition(g, en, f, 3, wpow=p))
         worst = max(worst, err)
-    _say(f"p = {p}: {en.n_face} faces, worst stencil rel err {worst:.2e} ({exact_checked} decided by the exact solve)")
+    _say(f"p = {p}: {en.n_face} faces, worst stencil rel err {worst:.2e}, {st.qr_faces} by QR")
 
 
 def test_weight_power_adjoint_matches_oracle():

@@ -92,3 +92,21 @@ def test_neighbours_match_hand_derived_rows(face):
         assert en.face_kind[f] == (S.KIND_BOX if kind == "box" else S.KIND_GRID)
     got = oracle.neighbours(en, f, R)
     assert list(got) == expected
+
+
+@pytest.mark.parametrize("case", ["maskA", "maskB", "circle16", "star32", "sphere8", "sphere8_r2"])
+def test_all_face_rows_at_once_match_face_by_face(case):
+    """neighbours_all (sparse reachability, used for the full-size bit-exact checks) gives
+    exactly the rows of neighbours() on every face."""
+    if case.startswith("mask"):
+        g, R = _mask_geometry(MASKS[case[-1]]), 2
+    else:
+        shape, n, Q, R = {"circle16": (cg.ball_outside((0.5, 0.5), 0.25), 16, 2, 2),
+                          "star32": (cg.star2_outside((0.5, 0.5), 0.25, 0.05, 6), 32, 4, 3),
+                          "sphere8": (cg.ball_outside((0.5, 0.5, 0.5), 0.3), 8, 4, 3),
+                          "sphere8_r2": (cg.ball_outside((0.5, 0.5, 0.5), 0.3), 8, 2, 2)}[case]
+        g = cg.make_geometry(shape, n, Q)
+    en = oracle.enumerate_geometry(g)
+    rp, col = oracle.neighbours_all(en, R)
+    for f in range(en.n_face):
+        assert list(col[rp[f]:rp[f + 1]]) == list(oracle.neighbours(en, f, R)), f
