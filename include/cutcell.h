@@ -222,6 +222,22 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
                            const cutcell_sizes* sizes, cutcell_stencils* out,
                            void* workspace, size_t workspace_bytes, cutcell_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): cutcell_build_stencils with the
+ * library's own scratch in place of the caller's workspace.  The scratch is one static
+ * device array of CUTCELL_STATIC_SCRATCH_BYTES per GPU, held from the library's loading to
+ * the end of the process; a batch whose workspace (cutcell_workspace_bytes) is larger is
+ * refused with CUTCELL_E_WORKSPACE before any work (96 MiB holds one geometry up to 64^3 at
+ * order 4).  The call allocates nothing and records no profiling events.  Every call on one
+ * GPU uses that GPU's array, which keeps the last call's contents (the build clears what it
+ * needs), so calls that overlap on one GPU -- other threads, other streams -- race and must
+ * be serialised by the caller.  `sizes` comes from cutcell_query (with a workspace of the
+ * caller's, e.g. at set-up).  Outputs and return codes as cutcell_build_stencils.
+ * Synchronises `stream`. */
+#define CUTCELL_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+int cutcell_build_stencils_noalloc(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                                   const cutcell_sizes* sizes, cutcell_stencils* out, cutcell_stream_t stream);
+
 /* Builds the stencils like cutcell_build_stencils and, on the way, times every candidate
  * schedule of each row-count bin (best of `reps` runs, HIP events on `stream`), writing the
  * fastest to *tuning and each bin's best time in milliseconds to best_ms[8] (-1 for empty

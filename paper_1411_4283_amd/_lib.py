@@ -38,6 +38,7 @@ BC_DIRICHLET = 0
 BC_NEUMANN = 1
 FACTOR_AUTO = 0
 FACTOR_QR = 1
+STATIC_SCRATCH_BYTES = 96 << 20   # CUTCELL_STATIC_SCRATCH_BYTES
 
 
 class Geom(ctypes.Structure):
@@ -163,6 +164,8 @@ SIGNATURES = {
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "cutcell_last_reused_faces": (ctypes.c_int64, []),
     "cutcell_last_qr_faces": (ctypes.c_int64, []),
+    "cutcell_build_stencils_noalloc": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts),
+                                                      ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P]),
     "cutcell_last_error": (ctypes.c_char_p, []),
     "cutcell_abi_version": (ctypes.c_int, []),
 }

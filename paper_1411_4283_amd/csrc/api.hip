@@ -1,6 +1,7 @@
 // Host entry points of the C ABI declared in include/cutcell.h.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,31 @@ int fail(int code, const std::string& msg) {
 }
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---- the static scratch of cutcell_build_stencils_noalloc ---------------------------------
+// One array per GPU, in this file's code object (the runtime places it on every device when
+// the library is loaded).  In host code `scratch` is only a stand-in for the symbol: its
+// device address comes from hipGetSymbolAddress, once per device with that device current,
+// and is what kernels and copies are given.
+constexpr size_t kStaticScratchBytes = CUTCELL_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static int static_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> ptrs;   // device address of `scratch`, per device
+  int dev = 0;
+  CC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    CC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(CUTCELL_E_HIP, "hipGetSymbolAddress returned no address for the static scratch");
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return CUTCELL_OK;
+}
 
 size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   Work t{};
@@ -392,6 +418,20 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
                            const cutcell_sizes* sizes, cutcell_stencils* out, void* workspace, size_t workspace_bytes,
                            cutcell_stream_t stream) {
   return build_common(geoms, n_geom, opts, sizes, out, workspace, workspace_bytes, stream, nullptr, 0, nullptr);
+}
+
+int cutcell_build_stencils_noalloc(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
+                                   const cutcell_sizes* sizes, cutcell_stencils* out, cutcell_stream_t stream) {
+  int rc = validate(geoms, n_geom, opts);
+  if (rc) return rc;
+  const size_t need = layout_work(*opts, n_geom, nullptr, nullptr);
+  if (need > kStaticScratchBytes)
+    return fail(CUTCELL_E_WORKSPACE, "the build needs " + std::to_string(need) + " bytes of scratch; the static " +
+                                         "scratch holds " + std::to_string(kStaticScratchBytes));
+  void* ws = nullptr;
+  rc = static_scratch(&ws);
+  if (rc) return rc;
+  return build_common(geoms, n_geom, opts, sizes, out, ws, kStaticScratchBytes, stream, nullptr, 0, nullptr, false);
 }
 
 int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts, const cutcell_sizes* sizes,
