@@ -587,7 +587,8 @@ def qr_all_timings(torch, cc, dg, R, st_ref, n_face, flops, reps=2):
     torch.cuda.empty_cache()
     return {"ms_per_build": ms, "faces_per_s": n_face / (ms * 1e-3), "tflops_lapack_count": flops / (ms * 1e-3) / 1e12,
             "max_rel_diff_vs_default_build": rel, "same_status": same_status,
-            "note": "every face by the QR path (one wave per face, B in shared memory, double-double rows and "
+            "note": "every face by the QR path (one wave per face, factors in shared memory, the exact B in a "
+                    "workspace slot, double-double rows and "
                     "residuals); the default build routes only ill-conditioned faces there"}
 
 

@@ -166,11 +166,15 @@ typedef struct {
                              of W A held in shared memory, with the rows and the
                              refinement residuals of the augmented system in
                              double-double arithmetic, so the stencil is correct to FP64
-                             rounding while cond(W A) * eps < 1.                        */
+                             rounding while cond(W A) * eps < 1;
+                           CUTCELL_FACTOR_GRAM: every face on the Gram path, none sent to
+                             QR (rank deficiency from its pivots); accurate to about
+                             1.5e-16 cond(W A) -- for callers that want every face by one
+                             method (e.g. finite differences of the stencils).          */
 } cutcell_opts;
 
 enum { CUTCELL_BC_DIRICHLET = 0, CUTCELL_BC_NEUMANN = 1 };
-enum { CUTCELL_FACTOR_AUTO = 0, CUTCELL_FACTOR_QR = 1 };
+enum { CUTCELL_FACTOR_AUTO = 0, CUTCELL_FACTOR_QR = 1, CUTCELL_FACTOR_GRAM = 2 };
 
 /* One geometry: device arrays in the layouts above. */
 typedef struct {
@@ -227,14 +231,14 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
  * library's own scratch in place of the caller's workspace.  The scratch is one static
  * device array of CUTCELL_STATIC_SCRATCH_BYTES per GPU, held from the library's loading to
  * the end of the process; a batch whose workspace (cutcell_workspace_bytes) is larger is
- * refused with CUTCELL_E_WORKSPACE before any work (96 MiB holds one geometry up to 64^3 at
+ * refused with CUTCELL_E_WORKSPACE before any work (160 MiB holds one geometry up to 64^3 at
  * order 4).  The call allocates nothing and records no profiling events.  Every call on one
  * GPU uses that GPU's array, which keeps the last call's contents (the build clears what it
  * needs), so calls that overlap on one GPU -- other threads, other streams -- race and must
  * be serialised by the caller.  `sizes` comes from cutcell_query (with a workspace of the
  * caller's, e.g. at set-up).  Outputs and return codes as cutcell_build_stencils.
  * Synchronises `stream`. */
-#define CUTCELL_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+#define CUTCELL_STATIC_SCRATCH_BYTES ((size_t)160 << 20)
 int cutcell_build_stencils_noalloc(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
                                    const cutcell_sizes* sizes, cutcell_stencils* out, cutcell_stream_t stream);
 

@@ -64,15 +64,39 @@ def _recentre_t(mom, delta, D, Q):
     return (coef * powers * mom[..., qi]) @ Pm
 
 
-class _Inputs:
-    """Leaf tensors for every input the stencils read."""
+class _Rows:
+    """Leaf tensors for the rows of one input array that one face reads, made on first use
+    (the gradient of a face touches only those rows, so it is formed on them and added into
+    the full-size gradient afterwards)."""
 
-    def __init__(self, geom):
-        t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float64, requires_grad=True)  # noqa: E731
-        self.vol = t(geom.vol_mom)
-        self.face = [t(fm) for fm in geom.face_mom]
-        self.eb = t(geom.eb_mom) if len(geom.eb_cell) else torch.zeros((0, geom.vol_mom.shape[1]), dtype=torch.float64)
-        self.ebn = t(geom.eb_nmom) if len(geom.eb_cell) else torch.zeros((0, geom.D, 1), dtype=torch.float64)
+    def __init__(self, arr, grad=True):
+        self.arr = arr
+        self.grad = grad
+        self.leaves = {}
+
+    def __getitem__(self, key):
+        i, rest = (int(key[0]), key[1:]) if isinstance(key, tuple) else (int(key), ())
+        t = self.leaves.get(i)
+        if t is None:
+            t = torch.tensor(np.asarray(self.arr[i]), dtype=torch.float64, requires_grad=self.grad)
+            self.leaves[i] = t
+        return t[rest] if rest else t
+
+    def add_grad_to(self, out):
+        for i, t in self.leaves.items():
+            if t.grad is not None:
+                out[i] += t.grad.numpy()
+
+
+class _Inputs:
+    """The inputs the stencils read: volume, grid-face, EB and EB-normal moments, as leaf
+    rows (grad=True) or constant rows."""
+
+    def __init__(self, geom, grad=True):
+        self.vol = _Rows(geom.vol_mom, grad)
+        self.face = [_Rows(fm, grad) for fm in geom.face_mom]
+        self.eb = _Rows(geom.eb_mom, grad)
+        self.ebn = _Rows(geom.eb_nmom, grad)
 
 
 def _row_moments(inp, en, idx):
@@ -151,11 +175,11 @@ def stencils_backward(geom, en, R, row_ptr, val_bar, faces=None, weights=True, w
     """Gradient of sum_j val_bar[j] val[j] (val = h^(D-2) s~, the physical stencils) with
     respect to vol_mom, face_mom[d], eb_mom, eb_nmom, and (if `weights`) the weights (per
     nnz, holding the other inputs fixed).  Faces whose status is not OK contribute nothing."""
-    inp = _Inputs(geom)
     fl = range(en.n_face) if faces is None else faces
     hs = en.h ** (en.D - 2)
     w_bar = np.zeros(len(val_bar))
-    total = torch.zeros((), dtype=torch.float64)
+    out = dict(vol_mom=np.zeros(geom.vol_mom.shape), face_mom=[np.zeros(fm.shape) for fm in geom.face_mom],
+               eb_mom=np.zeros(np.shape(geom.eb_mom)), eb_nmom=np.zeros(np.shape(geom.eb_nmom)))
     for f in fl:
         f = int(f)
         a, b = int(row_ptr[f]), int(row_ptr[f + 1])
@@ -165,25 +189,22 @@ def stencils_backward(geom, en, R, row_ptr, val_bar, faces=None, weights=True, w
         idx0, s0, status = S.face_stencil(geom, en, f, R, wpow=wpow)
         if status != S.STATUS_OK:
             continue
+        inp = _Inputs(geom)
         s, W, idx = _face_stencil_t(inp, en, f, R, wpow=wpow)
-        total = total + hs * torch.sum(vb * s)
+        obj = hs * torch.sum(vb * s)
+        if obj.requires_grad:
+            obj.backward()
+        inp.vol.add_grad_to(out["vol_mom"])
+        for d in range(len(inp.face)):
+            inp.face[d].add_grad_to(out["face_mom"][d])
+        inp.eb.add_grad_to(out["eb_mom"])
+        inp.ebn.add_grad_to(out["eb_nmom"])
         if not weights:
             continue
         # weights as free leaves: d/dW of the same objective
         wl = W.detach().clone().requires_grad_(True)
-        s_w, _, _ = _face_stencil_t(_detached(inp), en, f, R, wleaf=wl, wpow=wpow)
+        s_w, _, _ = _face_stencil_t(_Inputs(geom, grad=False), en, f, R, wleaf=wl, wpow=wpow)
         gw, = torch.autograd.grad(hs * torch.sum(vb * s_w), wl)
         w_bar[a:b] = gw.numpy()
-    if total.requires_grad:
-        total.backward()
-    g = lambda t: (t.grad.numpy().copy() if t.grad is not None else np.zeros(tuple(t.shape)))  # noqa: E731
-    return dict(vol_mom=g(inp.vol), face_mom=[g(t) for t in inp.face], eb_mom=g(inp.eb), eb_nmom=g(inp.ebn),
-                weight=w_bar)
-
-
-class _detached:
-    def __init__(self, inp):
-        self.vol = inp.vol.detach()
-        self.face = [t.detach() for t in inp.face]
-        self.eb = inp.eb.detach()
-        self.ebn = inp.ebn.detach()
+    out["weight"] = w_bar
+    return out

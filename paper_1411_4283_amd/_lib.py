@@ -38,7 +38,8 @@ BC_DIRICHLET = 0
 BC_NEUMANN = 1
 FACTOR_AUTO = 0
 FACTOR_QR = 1
-STATIC_SCRATCH_BYTES = 96 << 20   # CUTCELL_STATIC_SCRATCH_BYTES
+FACTOR_GRAM = 2
+STATIC_SCRATCH_BYTES = 160 << 20   # CUTCELL_STATIC_SCRATCH_BYTES
 
 
 class Geom(ctypes.Structure):

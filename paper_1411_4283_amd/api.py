@@ -70,7 +70,7 @@ class DeviceGeometry:
 _BC = {"dirichlet": _lib.BC_DIRICHLET, "neumann": _lib.BC_NEUMANN}
 
 
-_FACTOR = {"auto": _lib.FACTOR_AUTO, "qr": _lib.FACTOR_QR}
+_FACTOR = {"auto": _lib.FACTOR_AUTO, "qr": _lib.FACTOR_QR, "gram": _lib.FACTOR_GRAM}
 
 
 def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = "dirichlet",
@@ -79,8 +79,8 @@ def make_opts(dim: int, n, h: float, order: int, path_radius: int, eb_bc: str = 
     """cutcell_opts; eb_bc: "dirichlet" or "neumann" on every embedded-boundary face;
     reuse_templates: copy the stencils of faces whose systems are bitwise identical;
     weight_power: the exponent p of W = (2d)^-p (None: the paper's 5);
-    factorization: "auto" (Gram path, ill-conditioned faces by Householder QR) or "qr"
-    (every face by Householder QR)."""
+    factorization: "auto" (Gram path, ill-conditioned faces by Householder QR), "qr"
+    (every face by Householder QR) or "gram" (every face on the Gram path)."""
     if eb_bc not in _BC:
         raise ValueError(f"eb_bc must be one of {sorted(_BC)}")
     if factorization not in _FACTOR:

@@ -68,10 +68,11 @@ class OperatorApply(torch.autograd.Function):
 
 class CutCellOperator:
     """L(Phi) for a batch of geometries that share a grid, differentiable with respect to
-    Phi and to every moment tensor (set requires_grad on the DeviceGeometry tensors)."""
+    Phi and to every moment tensor (set requires_grad on the DeviceGeometry tensors).
+    `options` go to the Builder (eb_bc, weight_power, factorization, ...)."""
 
-    def __init__(self, geoms, path_radius: int):
-        self.builder = Builder(geoms, path_radius)
+    def __init__(self, geoms, path_radius: int, **options):
+        self.builder = Builder(geoms, path_radius, **options)
 
     @property
     def geoms(self):

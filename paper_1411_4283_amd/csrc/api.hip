@@ -130,6 +130,11 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
   t.flagged = (int32_t*)take(sizeof(int32_t) * 2);
   t.qr_count = (int32_t*)take(sizeof(int32_t));
   t.qr_list = (int32_t*)take(sizeof(int32_t) * totface);
+  {
+    const int M = binom(o.order + o.dim, o.dim);
+    t.qr_slots = (int)std::min<long long>(kQrSlots, std::max<long long>(totface, 1));
+    t.qr_b = (double*)take(sizeof(double) * t.qr_slots * 2 * kMaxRows * (M | 1));
+  }
   t.geoms = (GeomPtrs*)take(sizeof(GeomPtrs) * G);
   t.bytes = off;
   if (w) *w = t;
@@ -148,8 +153,9 @@ static int validate(const cutcell_geom* geoms, int G, const cutcell_opts* o) {
     return fail(CUTCELL_E_INVALID_ARG, "weight_power must be in [0, 16]");
   if (o->reuse_templates != 0 && o->reuse_templates != 1)
     return fail(CUTCELL_E_INVALID_ARG, "reuse_templates must be 0 or 1");
-  if (o->factorization != CUTCELL_FACTOR_AUTO && o->factorization != CUTCELL_FACTOR_QR)
-    return fail(CUTCELL_E_INVALID_ARG, "factorization must be CUTCELL_FACTOR_AUTO or CUTCELL_FACTOR_QR");
+  if (o->factorization != CUTCELL_FACTOR_AUTO && o->factorization != CUTCELL_FACTOR_QR &&
+      o->factorization != CUTCELL_FACTOR_GRAM)
+    return fail(CUTCELL_E_INVALID_ARG, "factorization must be CUTCELL_FACTOR_AUTO, _QR or _GRAM");
   if (o->eb_bc != CUTCELL_BC_DIRICHLET && o->eb_bc != CUTCELL_BC_NEUMANN)
     return fail(CUTCELL_E_INVALID_ARG, "eb_bc must be CUTCELL_BC_DIRICHLET or CUTCELL_BC_NEUMANN");
   if (o->tuning)

@@ -15,6 +15,7 @@ constexpr int kNBuckets = kMaxBins + 2;   // then faces with N < M, then templat
 constexpr int kPartWords = 2 * kNBuckets + 1;      // counts, cursors, max rows; then per row bin
 constexpr int kBinWords = kPartWords + 2 * kMaxBins;  // the faces of its part 0 and of its part 1
 constexpr int kXcds = 8;        // MI355X: workgroups are dealt to 8 XCDs (own L2 each) in turn
+constexpr int kQrSlots = 1024;  // workgroups of the QR path, each with a slot of workspace
 
 // Per-batch workspace: pointers into the caller's buffer.
 struct Work {
@@ -56,6 +57,8 @@ struct Work {
   int32_t* flagged;     // [2] flagged faces, bad EB input
   int32_t* qr_count;    // [1] faces left to the Householder QR path
   int32_t* qr_list;     // [G*maxface] those faces
+  double* qr_b;         // [qr_slots][2][kMaxRows * MS] the QR path's exact B per workgroup
+  int qr_slots;         // min(kQrSlots, G*maxface)
   GeomPtrs* geoms;      // [G]
   size_t bytes;
 };

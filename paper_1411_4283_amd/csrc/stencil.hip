@@ -74,6 +74,12 @@ static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_cou
   for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
   const bool neu = o.eb_bc == CUTCELL_BC_NEUMANN;
   const bool qr_all = !bw && o.factorization == CUTCELL_FACTOR_QR;
+  const bool route = o.factorization != CUTCELL_FACTOR_GRAM;
+  BinSchedule sc[kMaxBins];
+  for (int b = 0; b < kMaxBins; ++b) {
+    sc[b] = sched[b];
+    sc[b].route = route;
+  }
   int rc = CUTCELL_E_UNSUPPORTED;
   if (!bw) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.qr_count, 1LL, 0);
   if (qr_all) {
@@ -89,14 +95,14 @@ static int run_bins(const Work& w, const cutcell_opts& o, const int32_t* bin_cou
   } else {
 #define CC_RB(DD, QQ) \
   if (o.dim == DD && o.order == QQ) \
-    rc = dispatch_row_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sched, only_bin, neu, o.h, \
+    rc = dispatch_row_bins<DD, QQ>(w, hscale, bin_count, row_ptr, col, val, status, st, bw, sc, only_bin, neu, o.h, \
                                    o.weight_custom ? o.weight_power : 5.0);
     CC_RB(2, 2) CC_RB(2, 4) CC_RB(3, 2) CC_RB(3, 4)
 #undef CC_RB
     if (rc == CUTCELL_E_UNSUPPORTED) return fail(CUTCELL_E_UNSUPPORTED, "order/dimension");
     if (rc != CUTCELL_OK) return rc;
     // the faces the Gram path left to Householder QR (their count is on the device)
-    if (!bw) {
+    if (!bw && route) {
       rc = solve_qr_faces(w, o, w.qr_list, w.qr_count, 0, row_ptr, col, val, status, st);
       if (rc != CUTCELL_OK) return rc;
     }

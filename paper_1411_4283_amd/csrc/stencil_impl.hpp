@@ -45,6 +45,7 @@ namespace cutcell {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 constexpr double kRouteTol = 1e-4;
+constexpr double kRankTol = 1e-12;       // rank deficiency: min |R_kk| <= kRankTol max |R_kk|
 constexpr double kCondRoute = 3e4;
 constexpr double kSmallCell = 1e-3;      // rows (and EB flux vectors) of smaller cells in double-double
 constexpr double kSettleTol = 1e-6;
@@ -321,7 +322,8 @@ template <int D, int Q, int NPAD, bool NEU, class SM>
 __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& gp, const FaceInfo& fi,
                                             const int32_t* __restrict__ vol_cell, const int32_t* __restrict__ box_lf,
                                             const int32_t* __restrict__ col, SM& sm, int lane, double* a,
-                                            double& sdiag, double* wreg, double* zreg, double wpow) {
+                                            double& sdiag, double* wreg, double* zreg, double wpow,
+                                            bool* rank_low = nullptr) {
   using DM = Dims<D, Q>;
   constexpr int M = DM::M, MS = DM::MS;
   double* Bs = sm.Bs;
@@ -554,6 +556,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     smax = fmax(smax, __shfl_xor(smax, o));
   }
   const bool settled = dlast <= kSettleTol * smax;
+  if (rank_low) *rank_low = !((pmin > kRankTol * pmax) && (pmax > 0.0));
   if (!allfinite) return CUTCELL_STATUS_NONFINITE;
   if (!pivots_ok || !cond_ok || !settled) return kStatusRoute;
   return CUTCELL_STATUS_OK;
@@ -582,6 +585,7 @@ struct StencilArgs {
   double wpow;         // weight exponent p of W = (2 |delta|)^-p
   int32_t* qr_list;    // faces left to the Householder QR path, and their count
   int32_t* qr_count;
+  int route;           // 1: such faces go to the QR path; 0: the Gram path keeps every face
 };
 
 // Faces of a bin taken by workgroup blockIdx.x in turn (-1 when done).  With xcd = 1 and a
@@ -632,12 +636,16 @@ __device__ __forceinline__ void stencil_face(const StencilArgs& A, long long t, 
   face_x0<D, Q>(A.g, gp, fi);
   double a[M], wreg[NR], zreg[NR];
   double sdiag;
-  const int st = face_forward<D, Q, NPAD, NEU>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
-                                               A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a,
-                                               sdiag, wreg, zreg, A.wpow);
-  if (st == kStatusRoute) {   // the QR path writes this face's values and status
-    if (lane == 0) A.qr_list[atomicAdd(A.qr_count, 1)] = fi.F;
-    return;
+  bool rank_low = false;
+  int st = face_forward<D, Q, NPAD, NEU>(A.g, gp, fi, A.vol_cell_ws + (long long)fi.gi * A.g.ncell,
+                                         A.box_lf_ws + (long long)fi.gi * A.g.nboxslot, A.col, sm, lane, a, sdiag,
+                                         wreg, zreg, A.wpow, &rank_low);
+  if (st == kStatusRoute) {
+    if (A.route) {   // the QR path writes this face's values and status
+      if (lane == 0) A.qr_list[atomicAdd(A.qr_count, 1)] = fi.F;
+      return;
+    }
+    st = rank_low ? CUTCELL_STATUS_RANK_DEFICIENT : CUTCELL_STATUS_OK;
   }
   static_for<0, NR>([&](auto R) {
     const int r = lane + 64 * R;
@@ -921,6 +929,7 @@ inline StencilArgs stencil_args(const Work& w, double hscale, const int32_t* per
   A.wpow = 5.0;
   A.qr_list = w.qr_list;
   A.qr_count = w.qr_count;
+  A.route = 1;
   return A;
 }
 
@@ -929,6 +938,7 @@ inline StencilArgs stencil_args(const Work& w, double hscale, const int32_t* per
 struct BinSchedule {
   int xcd = 1;
   int per_xcd = 0;
+  bool route = true;   // faces the Gram path cannot resolve go to the QR path
 };
 
 template <int D, int Q, int NPAD, bool FWD_ONLY = false>
@@ -949,6 +959,7 @@ static void launch_bin(const Work& w, double hscale, const int32_t* perm, long l
   const long long per = sc.per_xcd > 0 ? std::min<long long>(sc.per_xcd, chunk) : chunk;
   A.xcd = X;
   A.per_xcd = (int)per;
+  A.route = sc.route ? 1 : 0;
   if (neu) {   // one workgroup per face (no persistent instance of the Neumann kernel)
     A.per_xcd = (int)chunk;
     A.h = h;

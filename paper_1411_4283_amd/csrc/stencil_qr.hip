@@ -11,7 +11,7 @@ int solve_qr_faces(const Work& w, const cutcell_opts& o, const int32_t* list, co
   int dev = 0, cus = 256;
   CC_HIP(hipGetDevice(&dev));
   CC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  long long grid = 2LL * cus;   // one face at a time per workgroup; the shared memory allows ~1 per CU
+  long long grid = std::min<long long>(4LL * cus, w.qr_slots);   // 4 per CU (shared memory, registers)
   if (!count_dev) grid = std::min(grid, count_host);
   double hscale = 1.0;
   for (int d = 0; d < o.dim - 2; ++d) hscale *= o.h;   // h^(D-2)
@@ -23,10 +23,10 @@ int solve_qr_faces(const Work& w, const cutcell_opts& o, const int32_t* list, co
 #define CC_QR(DD, QQ)                                                                                           \
   if (o.dim == DD && o.order == QQ) {                                                                           \
     if (neu)                                                                                                    \
-      hipLaunchKernelGGL((k_stencil_qr<DD, QQ, true>), g, b, 0, st, A, list, count_dev, count_host, val, status, \
-                         w.flagged);                                                                            \
+      hipLaunchKernelGGL((k_stencil_qr<DD, QQ, true>), g, b, 0, st, A, list, count_dev, count_host, w.qr_b, val, \
+                         status, w.flagged);                                                                            \
     else                                                                                                        \
-      hipLaunchKernelGGL((k_stencil_qr<DD, QQ, false>), g, b, 0, st, A, list, count_dev, count_host, val,       \
+      hipLaunchKernelGGL((k_stencil_qr<DD, QQ, false>), g, b, 0, st, A, list, count_dev, count_host, w.qr_b, val, \
                          status, w.flagged);                                                                    \
     CC_HIP(hipGetLastError());                                                                                  \
     return CUTCELL_OK;                                                                                          \

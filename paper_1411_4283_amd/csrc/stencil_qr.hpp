@@ -4,7 +4,8 @@
 // refinement that has not settled (k_stencil routes them here), and every face when the
 // caller asks for this factorisation.
 //
-// One wavefront owns one face, B lives in shared memory:
+// One wavefront owns one face; the factors live in shared memory, the exact B in a slot of
+// the workspace:
 //   1. rows in double-double: the offsets (x_i - x0)/h (exact half-integers for grid and
 //      box faces; for an EB face x0 = cell centre + first moments / zeroth moment), the
 //      binomial re-centring and the division by the zeroth moment carry ~106 bits, so B
@@ -20,35 +21,48 @@
 //      (g = Q^T r1, a = R^-T r2, dy = R^-1 (a - g1), dz = Q [a; g2]), repeated until the
 //      correction no longer changes z (at most kQrRefine times).  With residuals this
 //      accurate the iteration converges to z rounded to FP64 as long as cond(B) eps < 1.
-//   5. val = h^(D-2) W z; status RANK_DEFICIENT when min|R_kk| <= kQrRankTol max|R_kk|.
+//   5. val = h^(D-2) W z; status RANK_DEFICIENT when min|R_kk| <= kRankTol max|R_kk|.
 #pragma once
 
 #include "stencil_impl.hpp"
 
 namespace cutcell {
 
-constexpr double kQrRankTol = 1e-12;
 constexpr int kQrRefine = 6;
 
-// ---- wave reductions (butterfly: every lane ends with the same, fixed-order result) -------
+// ---- wave reductions --------------------------------------------------------------------
+// Within each row of 16 lanes by DPP moves (quad swaps, then the 8- and 16-lane mirrors),
+// which leave every lane of the row with the same partial result; then the four row
+// results in lane order.  Every lane returns the same value, in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum_f64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 __device__ __forceinline__ double wave_max_f64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x141>(v));
+  v = fmax(v, dpp_f64<0x140>(v));
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 template <int D, int Q>
 struct QrSmem {
   static constexpr int M = Dims<D, Q>::M, MS = Dims<D, Q>::MS, M1 = Dims<D, Q>::M1;
   double Bq[kMaxRows * MS];   // Householder factors: R on and above the diagonal, v below
-  double Bh[kMaxRows * MS];   // B = W A~ (columns scaled), high parts
-  double Bl[kMaxRows * MS];   //                             low parts
   double part[64];            // partial dot products of one step
   double wv[M];               // dot products of the pivot column with the trailing columns
   double tau[M];
+  double rdiag[M];            // 1 / R_kk
   double colsc[M];            // column scales (powers of two)
   double zs[kMaxRows];        // z, for B^T z
   double nuh[D][M1];          // EB normal moments about x0, high and low parts
@@ -93,7 +107,7 @@ template <int D, int Q>
 __device__ __forceinline__ double solve_rt(const QrSmem<D, Q>& sm, int lane, double x) {
   constexpr int M = Dims<D, Q>::M, MS = Dims<D, Q>::MS;
   for (int k = 0; k < M; ++k) {
-    const double ak = readlane_f64(x, k) / sm.Bq[k * MS + k];
+    const double ak = readlane_f64(x, k) * sm.rdiag[k];
     if (lane == k) x = ak;
     else if (lane > k && lane < M) x = fma(-sm.Bq[k * MS + lane], ak, x);
   }
@@ -105,7 +119,7 @@ template <int D, int Q>
 __device__ __forceinline__ double solve_r(const QrSmem<D, Q>& sm, int lane, double x) {
   constexpr int M = Dims<D, Q>::M, MS = Dims<D, Q>::MS;
   for (int k = M - 1; k >= 0; --k) {
-    const double yk = readlane_f64(x, k) / sm.Bq[k * MS + k];
+    const double yk = readlane_f64(x, k) * sm.rdiag[k];
     if (lane == k) x = yk;
     else if (lane < k) x = fma(-sm.Bq[lane * MS + k], yk, x);
   }
@@ -113,8 +127,9 @@ __device__ __forceinline__ double solve_r(const QrSmem<D, Q>& sm, int lane, doub
 }
 
 template <int D, int Q, bool NEU>
-__device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int lane, double* __restrict__ val,
-                        int8_t* __restrict__ status, int32_t* flagged) {
+__device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, double* __restrict__ Bh,
+                        double* __restrict__ Bl, int lane, double* __restrict__ val, int8_t* __restrict__ status,
+                        int32_t* flagged) {
   using DM = Dims<D, Q>;
   constexpr int M = DM::M, MS = DM::MS, M1 = DM::M1;
   FaceInfo fi = face_info_of(A, F);
@@ -139,8 +154,8 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
       finite = dd_row<D, Q, NEU>(gp, rs, x0, A.wpow, m, w) && finite;
       wreg[R] = w;
       static_for<0, M>([&](auto I) {
-        sm.Bh[r * MS + I] = m[I].hi;
-        sm.Bl[r * MS + I] = m[I].lo;
+        Bh[r * MS + I] = m[I].hi;
+        Bl[r * MS + I] = m[I].lo;
       });
     }
   });
@@ -199,7 +214,7 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
   bool zero_col = false;
   if (lane < M) {
     double c2 = 0.0;
-    for (int r = 0; r < N; ++r) c2 = fma(sm.Bh[r * MS + lane], sm.Bh[r * MS + lane], c2);
+    for (int r = 0; r < N; ++r) c2 = fma(Bh[r * MS + lane], Bh[r * MS + lane], c2);
     zero_col = !(c2 > 0.0);
     sm.colsc[lane] = (c2 > 0.0 && isfinite(c2)) ? ldexp(1.0, -ilogb(sqrt(c2))) : 1.0;
   }
@@ -215,9 +230,9 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
     if (r < N) {
       static_for<0, M>([&](auto I) {
         const double s = sm.colsc[I];
-        const double h = sm.Bh[r * MS + I] * s;
-        sm.Bh[r * MS + I] = h;
-        sm.Bl[r * MS + I] *= s;
+        const double h = Bh[r * MS + I] * s;
+        Bh[r * MS + I] = h;
+        Bl[r * MS + I] *= s;
         sm.Bq[r * MS + I] = h;
       });
     }
@@ -237,10 +252,18 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
       const int jj = lane / G, g = lane - jj * G;
       const bool act = jj < m;
       const int j = k + jj;
-      double part = 0.0;
-      if (act)
-        for (int r = k + 1 + g; r < N; r += G) part = fma(sm.Bq[r * MS + k], sm.Bq[r * MS + j], part);
-      sm.part[lane] = part;
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;   // four chains keep loads in flight
+      if (act) {
+        int r = k + 1 + g;
+        for (; r + 3 * G < N; r += 4 * G) {
+          p0 = fma(sm.Bq[r * MS + k], sm.Bq[r * MS + j], p0);
+          p1 = fma(sm.Bq[(r + G) * MS + k], sm.Bq[(r + G) * MS + j], p1);
+          p2 = fma(sm.Bq[(r + 2 * G) * MS + k], sm.Bq[(r + 2 * G) * MS + j], p2);
+          p3 = fma(sm.Bq[(r + 3 * G) * MS + k], sm.Bq[(r + 3 * G) * MS + j], p3);
+        }
+        for (; r < N; r += G) p0 = fma(sm.Bq[r * MS + k], sm.Bq[r * MS + j], p0);
+      }
+      sm.part[lane] = (p0 + p1) + (p2 + p3);
       __syncthreads();
       if (act && g == 0) {
         double s = 0.0;
@@ -259,7 +282,21 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
       if (act) {
         // v^T C_j = C_kj + inv * (x below k)^T C_j;  C_rj -= tau v_r (v^T C_j)
         const double tsj = (j > k) ? tau * fma(sm.wv[j], inv, sm.Bq[k * MS + j]) : 0.0;
-        for (int r = k + g; r < N; r += G) {
+        int r = k + g;
+        for (; r + 3 * G < N; r += 4 * G) {   // four rows: every load before any store
+          double x[4], c[4];
+          static_for<0, 4>([&](auto U) {
+            x[U] = sm.Bq[(r + U * G) * MS + k];
+            c[U] = sm.Bq[(r + U * G) * MS + j];
+          });
+          static_for<0, 4>([&](auto U) {
+            const int rr = r + U * G;
+            const double vr = (rr == k) ? 1.0 : x[U] * inv;
+            if (j > k) sm.Bq[rr * MS + j] = fma(-tsj, vr, c[U]);
+            else sm.Bq[rr * MS + k] = (rr == k) ? beta : vr;
+          });
+        }
+        for (; r < N; r += G) {
           const double vr = (r == k) ? 1.0 : sm.Bq[r * MS + k] * inv;
           if (j > k) sm.Bq[r * MS + j] = fma(-tsj, vr, sm.Bq[r * MS + j]);
           else sm.Bq[r * MS + k] = (r == k) ? beta : vr;
@@ -270,7 +307,9 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
       rmin = fmin(rmin, fabs(beta));
       __syncthreads();
     }
-    if (!(rmin > kQrRankTol * rmax)) st = CUTCELL_STATUS_RANK_DEFICIENT;
+    if (!(rmin > kRankTol * rmax)) st = CUTCELL_STATUS_RANK_DEFICIENT;
+    if (lane < M) sm.rdiag[lane] = 1.0 / sm.Bq[lane * MS + lane];
+    __syncthreads();
   }
 
   // ---- minimum-norm solution by refinement of the augmented system -------------------------
@@ -278,25 +317,41 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
   double yl = 0.0;   // lane p: y_p
   if (st == CUTCELL_STATUS_OK) {
     for (int it = 0; it < kQrRefine; ++it) {
-      // r1 = B y - z (rows) and r2 = F~ - B^T z (columns), in double-double
+      // r1 = B y - z (rows) and r2 = F~ - B^T z (columns), with B = Bh + Bl: the Bh terms in
+      // compensated arithmetic (Dot2, two chains), the Bl terms (below 2^-53 of them) plainly
       double r1[2] = {0.0, 0.0};
       static_for<0, 2>([&](auto R) {
         const int r = lane + 64 * R;
-        dd acc = dd_from(-zr[R]);
+        Dot2 d0{-zr[R], 0.0}, d1{0.0, 0.0};
+        double lo = 0.0;
         static_for<0, M>([&](auto P) {
           const double yp = readlane_f64(yl, P);
-          if (r < N) acc = dd_add(acc, dd_mul_d(dd{sm.Bh[r * MS + P], sm.Bl[r * MS + P]}, yp));
+          if (r < N) {
+            if constexpr (P % 2 == 0) dot2_add(d0, Bh[r * MS + P], yp);
+            else dot2_add(d1, Bh[r * MS + P], yp);
+            lo = fma(Bl[r * MS + P], yp, lo);
+          }
         });
-        r1[R] = (r < N) ? acc.hi : 0.0;
+        r1[R] = (r < N) ? dot2_merge(d0, Dot2{d1.s, d1.c + lo}) : 0.0;
         if (r < N) sm.zs[r] = zr[R];
       });
       __syncthreads();
       double r2 = 0.0;
       if (lane < M) {
-        dd acc = fv;
-        for (int r = 0; r < N; ++r)
-          acc = dd_sub(acc, dd_mul_d(dd{sm.Bh[r * MS + lane], sm.Bl[r * MS + lane]}, sm.zs[r]));
-        r2 = acc.hi;
+        Dot2 d0{fv.hi, fv.lo}, d1{0.0, 0.0};
+        double lo = 0.0;
+        int r = 0;
+        for (; r + 1 < N; r += 2) {
+          dot2_add(d0, -Bh[r * MS + lane], sm.zs[r]);
+          dot2_add(d1, -Bh[(r + 1) * MS + lane], sm.zs[r + 1]);
+          lo = fma(-Bl[r * MS + lane], sm.zs[r], lo);
+          lo = fma(-Bl[(r + 1) * MS + lane], sm.zs[r + 1], lo);
+        }
+        if (r < N) {
+          dot2_add(d0, -Bh[r * MS + lane], sm.zs[r]);
+          lo = fma(-Bl[r * MS + lane], sm.zs[r], lo);
+        }
+        r2 = dot2_merge(d0, Dot2{d1.s, d1.c + lo});
       }
       __syncthreads();
       // g = Q^T r1;  a = R^-T r2;  dy = R^-1 (a - g1);  dz = Q [a; g2]
@@ -340,17 +395,23 @@ __device__ void qr_face(const StencilArgs& A, int32_t F, QrSmem<D, Q>& sm, int l
 }
 
 // The faces list[0 .. n) (n from the device when count_dev is given), each by one
-// workgroup of one wave in turn; the grid walks the list.
+// workgroup of one wave in turn; the grid (at most kQrSlots workgroups) walks the list.
+// Workgroup b keeps the exact B of its face (high and low parts, read only by the
+// refinement residuals) in slot b of bslots, kMaxRows * MS doubles each; shared memory
+// holds the factors, so that four faces fit on a CU.
 template <int D, int Q, bool NEU>
 __global__ __launch_bounds__(64) void k_stencil_qr(StencilArgs A, const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ count_dev, long long count_host,
-                                                  double* __restrict__ val, int8_t* __restrict__ status,
-                                                  int32_t* flagged) {
+                                                  double* __restrict__ bslots, double* __restrict__ val,
+                                                  int8_t* __restrict__ status, int32_t* flagged) {
+  constexpr int MS = Dims<D, Q>::MS;
   __shared__ QrSmem<D, Q> sm;
+  double* Bh = bslots + (long long)blockIdx.x * 2 * kMaxRows * MS;
+  double* Bl = Bh + kMaxRows * MS;
   const long long n = count_dev ? (long long)*count_dev : count_host;
   for (long long t = blockIdx.x; t < n; t += gridDim.x) {
-    qr_face<D, Q, NEU>(A, list[t], sm, threadIdx.x, val, status, flagged);
-    __syncthreads();   // the next face reuses the shared memory
+    qr_face<D, Q, NEU>(A, list[t], sm, Bh, Bl, threadIdx.x, val, status, flagged);
+    __syncthreads();   // the next face reuses the shared memory and the slot
   }
 }
 
