@@ -134,6 +134,10 @@ size_t layout_work(const cutcell_opts& o, int G, char* base, Work* w) {
     const int M = binom(o.order + o.dim, o.dim);
     t.qr_slots = (int)std::min<long long>(kQrSlots, std::max<long long>(totface, 1));
     t.qr_b = (double*)take(sizeof(double) * t.qr_slots * 2 * kMaxRows * (M | 1));
+    // ballot masks of the neighbour window, (2R + 2)(2R + 1)^(D-1) cells, per face
+    long long nw = 2 * o.path_radius + 2;
+    for (int d = 1; d < o.dim; ++d) nw *= 2 * o.path_radius + 1;
+    t.nbmask = (unsigned long long*)take(sizeof(unsigned long long) * totface * ((nw + 63) / 64));
   }
   t.geoms = (GeomPtrs*)take(sizeof(GeomPtrs) * G);
   t.bytes = off;

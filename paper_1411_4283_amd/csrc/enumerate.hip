@@ -296,7 +296,8 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
                                                    const int32_t* __restrict__ box_id, const int64_t* __restrict__ counts,
                                                    const int64_t* __restrict__ offs, const uint8_t* __restrict__ cellinfo,
                                                    const uint8_t* __restrict__ ballreg, int32_t* nrows,
-                                                   const int64_t* __restrict__ row_ptr, int32_t* col, int neumann) {
+                                                   const int64_t* __restrict__ row_ptr, int32_t* col, int neumann,
+                                                   unsigned long long* __restrict__ nbmask) {
   using W = Win<D, R>;
   __shared__ int8_t dist[W::NW];
   const long long F = blockIdx.x;
@@ -364,6 +365,10 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
   }
   const int NW = ext[0] * ext[1] * ext[2];
 
+  // the fill pass takes the rows the count pass found (its ballot masks, one word per 64
+  // window cells, at the face's own slot) instead of searching again
+  const bool reuse = FILL && nbmask;
+
   // per-lane window cells: global cell, info byte (volume, open faces, EB); open bits
   // are kept only toward neighbours inside the window and the box
   const uint8_t* inf = cellinfo + (long long)gi * g.ncell;
@@ -402,6 +407,7 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
     }
     if (!inbox) continue;
     cell[k] = cell_index(g, x);
+    if (reuse) continue;   // rows from the count pass: no search
     info[k] = inf[cell[k]];
     isvol[k] = info[k] & 1u;
     for (int ax = 0; ax < D; ++ax)
@@ -412,6 +418,12 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
           open[k] |= 1u << (2 * ax + s);
       }
   }
+  bool inS[W::K];
+  if (reuse) {
+    const unsigned long long* mk = nbmask + F * W::K;
+#pragma unroll
+    for (int k = 0; k < W::K; ++k) inS[k] = (mk[k] >> lane) & 1ull;
+  } else {
   // distances: 0 at the adjacent volumes, R + 1 ("far") elsewhere
 #pragma unroll
   for (int k = 0; k < W::K; ++k) {
@@ -447,11 +459,11 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
       if (nd[k] > 0) dist[lane + 64 * k] = nd[k];
     __syncthreads();
   }
-  bool inS[W::K];
 #pragma unroll
   for (int k = 0; k < W::K; ++k) {
     const int w = lane + 64 * k;
     inS[k] = (w < NW) && isvol[k] && dist[w] <= R;
+  }
   }
 
   const int64_t* cnt = counts + 4 * gi;
@@ -469,6 +481,14 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if (lane == 0) nrows[F] = c;
+    if (nbmask) {   // leave the rows for the fill pass
+      unsigned long long* mk = nbmask + F * W::K;
+#pragma unroll
+      for (int k = 0; k < W::K; ++k) {
+        const unsigned long long m = __ballot(inS[k]);
+        if (lane == k) mk[k] = m;
+      }
+    }
     return;
   }
   // fill in ascending Phi order: volumes, EB faces, box faces by (d, side)
@@ -512,14 +532,15 @@ __global__ __launch_bounds__(64) void k_neighbours(GridDims g, int G, long long 
 template <int D, int R>
 static void launch_neighbours(const Work& w, long long n_face, const int64_t* row_ptr, int32_t* col, bool fill,
                               int neumann, hipStream_t st) {
+  // the count pass leaves each searched face's rows (as ballot masks) for the fill pass
   if (fill)
     hipLaunchKernelGGL((k_neighbours<D, R, true>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
                        w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
-                       w.ballreg, w.nrows, row_ptr, col, neumann);
+                       w.ballreg, w.nrows, row_ptr, col, neumann, w.nbmask);
   else
     hipLaunchKernelGGL((k_neighbours<D, R, false>), dim3((unsigned)n_face), dim3(64), 0, st, w.dims, w.G, n_face,
                        w.fcode, w.fref, w.geoms, w.vol_id, w.eb_id, w.face_id, w.box_id, w.counts, w.offs, w.cellinfo,
-                       w.ballreg, w.nrows, row_ptr, col, neumann);
+                       w.ballreg, w.nrows, row_ptr, col, neumann, w.nbmask);
 }
 
 int neighbour_rows(const Work& w, const cutcell_opts& o, long long n_face, const int64_t* row_ptr, int32_t* col,

@@ -58,6 +58,7 @@ struct Work {
   int32_t* qr_count;    // [1] faces left to the Householder QR path
   int32_t* qr_list;     // [G*maxface] those faces
   double* qr_b;         // [qr_slots][2][kMaxRows * MS] the QR path's exact B per workgroup
+  unsigned long long* nbmask;  // [G*maxface][window words] rows the count pass found (searched faces)
   int qr_slots;         // min(kQrSlots, G*maxface)
   GeomPtrs* geoms;      // [G]
   size_t bytes;
