@@ -49,6 +49,10 @@ constexpr double kRankTol = 1e-12;       // rank deficiency: min |R_kk| <= kRank
 constexpr double kCondRoute = 3e4;
 constexpr double kSmallCell = 1e-3;      // rows (and EB flux vectors) of smaller cells in double-double
 constexpr double kSettleTol = 1e-6;
+// Refinement residuals of faces whose bound on cond(G^) stays below this (cond(B) below
+// about 3e3) are summed in plain FP64: their rounding then moves the stencil by about
+// cond(B) eps < 1e-12 relative, and compensated sums cost ten times the instructions.
+constexpr double kDot2Cond = 1e7;
 constexpr int kRefine = 1;
 constexpr int kRefineBackward = 2;   // refinement steps of the adjoint's least-squares solve
 constexpr int kStatusRoute = 100;        // internal: the face goes to the QR path
@@ -493,9 +497,11 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     gnorm = fmax(gnorm, __shfl_xor(gnorm, o));
     inv2 += __shfl_xor(inv2, o);
   }
-  const bool cond_ok = gnorm * sqrt(inv2) <= kCondRoute * kCondRoute;
+  const double cbound = gnorm * sqrt(inv2);   // wave-uniform
+  const bool cond_ok = cbound <= kCondRoute * kCondRoute;
+  const bool dot2 = !(cbound <= kDot2Cond);
 
-  // ---- semi-normal solve with one compensated refinement step ---------------------------------
+  // ---- semi-normal solve with one refinement step (compensated residual past kDot2Cond) -------
   // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs).  Lane p holds
   // component p of F~, rhs and y; lane r holds z of its rows r, r + 64.
   double rhs = fv * sdiag;
@@ -520,7 +526,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
       }
     });
     if (it == kRefine) break;
-    // residual of B^T z = F~ in compensated arithmetic (two interleaved Dot2 sums); z goes
+    // residual of B^T z = F~ (two interleaved sums, compensated Dot2 ones past kDot2Cond); z goes
     // through LDS, B^T is read by columns
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
@@ -528,7 +534,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     });
     __syncthreads();
     double res = 0.0;
-    if (act) {
+    if (act && dot2) {
       Dot2 d0{fv, 0.0}, d1{0.0, 0.0};
 #pragma unroll 4
       for (int r = 0; r < NPAD; r += 2) {
@@ -536,6 +542,14 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
         dot2_add(d1, -Bs[(r + 1) * MS + lane], sm.zs[r + 1]);
       }
       res = dot2_merge(d0, d1);
+    } else if (act) {
+      double p0 = fv, p1 = 0.0;
+#pragma unroll 4
+      for (int r = 0; r < NPAD; r += 2) {
+        p0 = fma(-Bs[(r + 0) * MS + lane], sm.zs[r + 0], p0);
+        p1 = fma(-Bs[(r + 1) * MS + lane], sm.zs[r + 1], p1);
+      }
+      res = p0 + p1;
     }
     rhs = res * sdiag;
     __syncthreads();
