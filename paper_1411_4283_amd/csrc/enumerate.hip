@@ -740,12 +740,22 @@ __device__ __forceinline__ bool template_face(const GridDims& g, const int32_t* 
   return cn[b - st[dn]] && cn[b];
 }
 
+// The first template-able face of each (geometry, direction).  Faces of a wave are
+// consecutive and nearly always of one (geometry, direction): the wave's lowest such lane
+// stands for the lanes of its key (their minimum, faces ascending with the lane), and only
+// lanes of another key add their own atomic -- one atomic per wave instead of one per
+// face on three addresses per geometry.
 __global__ void k_tmpl_pick(GridDims g, long long n_face, const int32_t* __restrict__ fcode,
                             const int32_t* __restrict__ fref, const uint8_t* __restrict__ canon, int32_t* tface) {
   const long long F = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (F >= n_face) return;
-  int gi, dn;
-  if (template_face(g, fcode, fref, canon, F, &gi, &dn)) atomicMin(&tface[3 * gi + dn], (int32_t)F);
+  int gi = 0, dn = 0;
+  const bool q = F < n_face && template_face(g, fcode, fref, canon, F, &gi, &dn);
+  const unsigned long long m = __ballot(q);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
+  const int key = 3 * gi + dn;
+  const int lkey = __shfl(key, leader, 64);
+  if (q && (lane == leader || key != lkey)) atomicMin(&tface[key], (int32_t)F);
 }
 
 __global__ void k_tmpl_assign(GridDims g, long long n_face, const int32_t* __restrict__ fcode,
