@@ -286,7 +286,56 @@ def reuse_timings(torch, cc, dg, R, tuning, st_full, steps, n_face, full_ms):
     same = all(torch.equal(getattr(sr, k), getattr(st_full, k)) for k in ("row_ptr", "col", "val", "status"))
     return {"ms_per_step": ms, "faces_per_s": n_face / (ms * 1e-3), "speedup_vs_full_build": full_ms / ms,
             "solve_ms": sum(solve) / len(solve), "faces_copied": int(sr.reused), "faces_solved": int(n_face - sr.reused),
-            "bitwise_equal_to_full_build": bool(same)}
+            "bitwise_equal_to_full_build": bool(same), "packed_apply": packed_apply_timings(torch, cc, sr)}
+
+
+def packed_apply_timings(torch, cc, st, reps=20):
+    """The compressed stencils (template copies as a slot plus run bases) against the plain
+    CSR apply on the same stencils: HIP events on the launch stream, median of `reps`
+    each, outputs compared bit for bit.  Algorithmic bytes as for the plain apply, with
+    each packed face's entries replaced by its face, slot and run bases, plus the face
+    phases, the list of CSR faces and the slot tables."""
+    import numpy as np
+
+    s = st.sizes
+    dev = st.val.device
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    pk = cc.pack(st)
+    torch.cuda.synchronize()
+    pack_ms = (time.perf_counter() - t0) * 1e3
+    phi = torch.from_numpy(np.random.default_rng(2).standard_normal(s.n_phi)).to(dev)
+    lphi, flux = cc.apply(st, phi)
+    lphi2, flux2 = cc.apply_packed(st, pk, phi)
+
+    def med(fn):
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, z in ev:
+            a.record(stream)
+            fn()
+            z.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(z) for a, z in ev]))
+
+    plain_ms = med(lambda: cc.apply(st, phi, lphi, flux))
+    packed_ms = med(lambda: cc.apply_packed(st, pk, phi, lphi2, flux2))
+    same = torch.equal(lphi, lphi2) and torch.equal(flux, flux2)
+    rp = st.row_ptr.cpu().numpy()
+    flag = pk.flag[: s.n_face].cpu().numpy().astype(bool)
+    nnz_packed = int(np.sum(np.diff(rp)[flag]))
+    common = 8 * (s.n_face + 1) + 8 * s.n_phi + 16 * s.n_vol
+    plain_bytes = 12 * s.nnz + common
+    packed_bytes = 12 * (s.nnz - nnz_packed) + pk.bytes_per_apply() + common
+    return {"ms": packed_ms, "plain_apply_ms_same_stencils": plain_ms, "speedup_vs_plain_apply": plain_ms / packed_ms,
+            "bytes_per_launch": int(packed_bytes), "plain_bytes_per_launch": int(plain_bytes),
+            "gbps": packed_bytes / (packed_ms * 1e-3) / 1e9, "frac_of_hbm_peak": packed_bytes / (packed_ms * 1e-3)
+            / 1e9 / PEAK_HBM_GBS, "faces_packed": int(pk.sizes.n_packed), "entries_packed": nnz_packed,
+            "slots": int(pk.sizes.n_slot), "max_runs": int(pk.sizes.max_runs), "pack_ms": pack_ms,
+            "bitwise_equal_to_plain_apply": bool(same),
+            "note": "kernels k_apply_packed (CSR groups with packed faces skipped, then the packed faces) + "
+                    "k_divergence"}
 
 
 def laplacian_timings(torch, cc, st, phi, face_apply_ms, reps=20):
@@ -765,7 +814,8 @@ def main():
     }
     out["qr_faces"] = int(st.qr_faces)
     out["qr_faces_note"] = ("faces whose system the Gram path leaves to Householder QR (estimated cond of the "
-                            "equilibrated W A above 2e4, a pivot ratio below 1e-4, or an unsettled refinement)")
+                            "equilibrated W A above 3e4, a pivot ratio below 1e-4, or a refinement step above 1e-6 of the "
+                            "stencil)")
     if base is not None:
         out["parity_sample"] = parity_report(st, parity_ref)
         log(f"parity sample: {out['parity_sample']}")

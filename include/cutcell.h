@@ -88,7 +88,7 @@
 extern "C" {
 #endif
 
-#define CUTCELL_ABI_VERSION 11
+#define CUTCELL_ABI_VERSION 12
 
 enum {
   CUTCELL_OK = 0,
@@ -158,10 +158,13 @@ typedef struct {
                            'stencil equation solution'; the stencil is the same either
                            way, to the tolerance below):
                            CUTCELL_FACTOR_AUTO: the Gram matrix of the column-equilibrated
-                             W A (matrix cores), inverted, with two steps of refinement;
-                             a face whose smallest pivot is at most 1e-4 of the largest,
-                             or whose refinement has not settled to 2^-40 of the stencil,
-                             is solved again by the QR path;
+                             W A (matrix cores), inverted by Gauss-Jordan, with one step of
+                             refinement (its residual in compensated arithmetic when the
+                             estimated cond(W A) exceeds about 3e3; the rows of cells with
+                             kappa < 1e-3 in double-double); a face whose smallest pivot is
+                             at most 1e-4 of the largest, whose estimated cond(W A) exceeds
+                             3e4, or whose refinement step moved the stencil by more than
+                             1e-6 of its size, is solved again by the QR path;
                            CUTCELL_FACTOR_QR: every face by the QR path -- Householder QR
                              of W A held in shared memory, with the rows and the
                              refinement residuals of the augmented system in
@@ -169,8 +172,10 @@ typedef struct {
                              rounding while cond(W A) * eps < 1;
                            CUTCELL_FACTOR_GRAM: every face on the Gram path, none sent to
                              QR (rank deficiency from its pivots); accurate to about
-                             1.5e-16 cond(W A) -- for callers that want every face by one
-                             method (e.g. finite differences of the stencils).          */
+                             eps cond(W A) while the refinement converges -- for callers
+                             that want every face by one method (e.g. finite differences
+                             of the stencils, where a face changing path between the
+                             perturbed builds would show as noise).                     */
 } cutcell_opts;
 
 enum { CUTCELL_BC_DIRICHLET = 0, CUTCELL_BC_NEUMANN = 1 };
@@ -207,6 +212,9 @@ typedef struct {
   int64_t* phi_off;     /* [n_geom + 1] start of each geometry's Phi block              */
   int64_t* vol_off;     /* [n_geom + 1] start of each geometry's volumes                */
   int64_t* face_off;    /* [n_geom + 1] start of each geometry's flux faces             */
+  int32_t* tmpl;        /* [n_face] or NULL (then not written): the face whose stencil this
+                           face's was copied from (cutcell_opts.reuse_templates), -1 for a
+                           face solved itself -- the input of cutcell_pack_count           */
 } cutcell_stencils;
 
 /* Bytes of device workspace the calls below need for this grid and batch size. */
@@ -256,6 +264,58 @@ int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_op
  * phi: [n_phi], lphi: [n_vol].  Asynchronous on `stream`. */
 int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
                   const double* phi, double* lphi, double* flux, cutcell_stream_t stream);
+
+/* Compressed stencils for repeated applies (Sec. 4, standard interior stencils; Fig. 2b):
+ * a face whose stencil was copied from a template face (cutcell_opts.reuse_templates) is
+ * stored as its template's slot plus one Phi index per run of consecutive columns -- its
+ * values are the slot's (a copy of the template's row), its columns base[run] + position
+ * in the run -- instead of its own columns and values.  cutcell_pack_count checks every
+ * face against its template (st->tmpl) and packs it only where that reproduces its CSR
+ * row exactly (row count, columns, values bit for bit); the others stay CSR rows of `st`,
+ * which must stay as they are while the packed form is used. */
+typedef struct {
+  int64_t n_packed;   /* faces stored as a slot plus run bases                           */
+  int32_t n_slot;     /* template faces                                                  */
+  int32_t max_runs;   /* runs of consecutive columns per template, at most               */
+  int32_t max_rows;   /* rows per template, at most                                      */
+} cutcell_packed_sizes;
+
+typedef struct {
+  uint8_t* flag;      /* [n_face] 1: the face is packed                                  */
+  uint8_t* phase;     /* [n_face] lane of the face's first entry in cutcell_apply's flux
+                         pass (its row offset from the first face of its group, mod 64)  */
+  int32_t* face;      /* [n_packed] the packed faces, ascending                          */
+  int32_t* slot;      /* [n_packed] the slot of each one's template                      */
+  int32_t* base;      /* [n_packed][max_runs] Phi index of each run's first entry        */
+  int32_t* slot_face; /* [n_slot] the template face of each slot                         */
+  int32_t* slot_rows; /* [n_slot] its row count                                          */
+  int32_t* slot_tab;  /* [n_slot][max_rows] per entry: run | (position in the run) << 16 */
+  double* slot_val;   /* [n_slot][max_rows] its values                                   */
+} cutcell_packed;
+
+/* Bytes of workspace cutcell_pack_count and cutcell_pack_fill need. */
+size_t cutcell_pack_workspace_bytes(const cutcell_sizes* sizes);
+
+/* Counts the faces that pack and sizes the tables into *out.  st->tmpl is required.
+ * Synchronises `stream`. */
+int cutcell_pack_count(const cutcell_sizes* sizes, const cutcell_stencils* st, cutcell_packed_sizes* out,
+                       void* workspace, size_t workspace_bytes, cutcell_stream_t stream);
+
+/* Fills *out (arrays sized from *psizes, as cutcell_pack_count returned them for the same
+ * stencils; CUTCELL_E_CAPACITY if they no longer match) for applies in dimension `dim`
+ * (the phases follow that dimension's flux pass).  Synchronises `stream`. */
+int cutcell_pack_fill(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
+                      const cutcell_packed_sizes* psizes, cutcell_packed* out, void* workspace,
+                      size_t workspace_bytes, cutcell_stream_t stream);
+
+/* cutcell_apply on the compressed stencils (pk from cutcell_pack_fill on `st`, same dim):
+ * flux and lphi equal cutcell_apply's bit for bit -- every face's products are added in
+ * the order cutcell_apply adds them.  One launch takes the faces left as CSR rows of `st`
+ * (cutcell_apply's groups, packed faces skipped) and the packed ones.  Asynchronous on
+ * `stream`. */
+int cutcell_apply_packed(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st,
+                         const cutcell_packed_sizes* psizes, const cutcell_packed* pk, const double* phi,
+                         double* lphi, double* flux, cutcell_stream_t stream);
 
 /* Transposed structure of the stencils (for the adjoints): for every Phi entry k, the
  * CSR positions j with col[j] = k, ascending, in nz[col_ptr[k] .. col_ptr[k+1]), and the

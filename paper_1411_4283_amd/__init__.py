@@ -12,3 +12,4 @@ from .api import Transpose, apply_adjoint, build_transpose  # noqa: F401,E402
 from .autograd import CutCellOperator, OperatorApply, StencilBuild  # noqa: F401,E402
 from .api import Laplacian, SolveResult, apply_laplacian, build_laplacian, solve  # noqa: F401,E402
 from .api import hessenberg_eigs, ritz  # noqa: F401,E402
+from .api import Packed, apply_packed, pack  # noqa: F401,E402

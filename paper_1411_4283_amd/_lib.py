@@ -77,6 +77,30 @@ class StencilArrays(ctypes.Structure):
         ("phi_off", P),
         ("vol_off", P),
         ("face_off", P),
+        ("tmpl", P),
+    ]
+
+
+class PackedSizes(ctypes.Structure):
+    _fields_ = [
+        ("n_packed", ctypes.c_int64),
+        ("n_slot", ctypes.c_int32),
+        ("max_runs", ctypes.c_int32),
+        ("max_rows", ctypes.c_int32),
+    ]
+
+
+class PackedArrays(ctypes.Structure):
+    _fields_ = [
+        ("flag", P),
+        ("phase", P),
+        ("face", P),
+        ("slot", P),
+        ("base", P),
+        ("slot_face", P),
+        ("slot_rows", P),
+        ("slot_tab", P),
+        ("slot_val", P),
     ]
 
 
@@ -132,6 +156,14 @@ SIGNATURES = {
                                         ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P, ctypes.c_size_t,
                                         ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double), P]),
     "cutcell_apply": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays), P, P, P, P]),
+    "cutcell_pack_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
+    "cutcell_pack_count": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays),
+                                          ctypes.POINTER(PackedSizes), P, ctypes.c_size_t, P]),
+    "cutcell_pack_fill": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
+                                         ctypes.POINTER(PackedSizes), ctypes.POINTER(PackedArrays), P, ctypes.c_size_t,
+                                         P]),
+    "cutcell_apply_packed": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.c_int32, ctypes.POINTER(StencilArrays),
+                                            ctypes.POINTER(PackedSizes), ctypes.POINTER(PackedArrays), P, P, P, P]),
     "cutcell_transpose_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Sizes)]),
     "cutcell_build_transpose": (ctypes.c_int, [ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays),
                                                ctypes.POINTER(TransposeArrays), P, ctypes.c_size_t, P]),

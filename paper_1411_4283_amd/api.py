@@ -13,8 +13,8 @@ from math import comb
 import torch
 
 from . import _lib
-from ._lib import (OK, W_NOT_CONVERGED, Geom, GeomGrad, LaplacianArrays, Opts, Sizes, StencilArrays,
-                   TransposeArrays, Tuning, check, load)
+from ._lib import (OK, W_NOT_CONVERGED, Geom, GeomGrad, LaplacianArrays, Opts, PackedArrays, PackedSizes, Sizes,
+                   StencilArrays, TransposeArrays, Tuning, check, load)
 
 
 def _ptr(t: torch.Tensor | None) -> int | None:
@@ -116,6 +116,7 @@ class Stencils:
     phi_off: torch.Tensor
     vol_off: torch.Tensor
     face_off: torch.Tensor
+    tmpl: "torch.Tensor | None" = None   # [n_face] template of each copied face, else -1
     code: int = 0
     reused: int = 0            # faces whose stencil was copied from a template
     qr_faces: int = 0          # faces the Householder QR path solved
@@ -125,7 +126,8 @@ class Stencils:
     def struct(self, val: torch.Tensor | None = None, vol_scale: torch.Tensor | None = None) -> StencilArrays:
         """The C struct; `val` / `vol_scale` replace the stored arrays when given."""
         s = StencilArrays()
-        for name in ("row_ptr", "col", "val", "status", "vol_face", "vol_scale", "phi_off", "vol_off", "face_off"):
+        for name in ("row_ptr", "col", "val", "status", "vol_face", "vol_scale", "phi_off", "vol_off", "face_off",
+                     "tmpl"):
             setattr(s, name, _ptr(getattr(self, name)))
         if val is not None:
             _check_f64(val, self.sizes.nnz, "val")
@@ -270,6 +272,7 @@ class Builder:
             vol_face=torch.empty(max(s.n_vol, 1) * (2 * self.dim + 1), dtype=torch.int32, device=dev),
             vol_scale=torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=dev),
             phi_off=torch.empty(G + 1, **i64), vol_off=torch.empty(G + 1, **i64), face_off=torch.empty(G + 1, **i64),
+            tmpl=torch.empty(max(s.n_face, 1), dtype=torch.int32, device=dev),
         )
 
     def build(self, out: Stencils | None = None, stream=None) -> Stencils:
@@ -340,6 +343,78 @@ def apply(st: Stencils, phi: torch.Tensor, lphi: torch.Tensor | None = None, flu
     rc = load().cutcell_apply(ctypes.byref(s), st.dim, ctypes.byref(arr), _ptr(phi), _ptr(lphi), _ptr(flux),
                               _stream(stream))
     check(rc, "cutcell_apply", allow_flagged=False)
+    return lphi[: s.n_vol], flux[: s.n_face]
+
+
+@dataclass
+class Packed:
+    """Compressed stencils (cutcell_pack_*): template-copied faces as a slot plus run bases."""
+
+    sizes: PackedSizes
+    flag: torch.Tensor
+    phase: torch.Tensor
+    face: torch.Tensor
+    slot: torch.Tensor
+    base: torch.Tensor
+    slot_face: torch.Tensor
+    slot_rows: torch.Tensor
+    slot_tab: torch.Tensor
+    slot_val: torch.Tensor
+
+    def struct(self) -> PackedArrays:
+        s = PackedArrays()
+        for name in ("flag", "phase", "face", "slot", "base", "slot_face", "slot_rows", "slot_tab", "slot_val"):
+            setattr(s, name, _ptr(getattr(self, name)))
+        return s
+
+    def bytes_per_apply(self) -> int:
+        """Bytes the apply reads besides the CSR rows of the other faces: the flags, the
+        packed faces' ids, slots, phases and run bases, and the slot tables."""
+        p = self.sizes
+        return int(self.flag.numel()) + int(p.n_packed) * (9 + 4 * int(p.max_runs)) \
+            + int(p.n_slot) * int(p.max_rows) * 12
+
+
+def pack(st: Stencils, stream=None) -> Packed:
+    """Compress the stencils of a build with template reuse (count, then fill)."""
+    if st.tmpl is None:
+        raise ValueError("the stencils carry no tmpl array")
+    s = st.sizes
+    dev = st.val.device
+    lib = load()
+    nbytes = lib.cutcell_pack_workspace_bytes(ctypes.byref(s))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    ps = PackedSizes()
+    arr = st.struct()
+    check(lib.cutcell_pack_count(ctypes.byref(s), ctypes.byref(arr), ctypes.byref(ps), _ptr(ws), nbytes,
+                                 _stream(stream)), "cutcell_pack_count", allow_flagged=False)
+    i32 = dict(dtype=torch.int32, device=dev)
+    u8 = dict(dtype=torch.uint8, device=dev)
+    n, ns = int(ps.n_packed), int(ps.n_slot)
+    pk = Packed(ps, torch.empty(max(s.n_face, 1), **u8), torch.empty(max(s.n_face, 1), **u8),
+                torch.empty(max(n, 1), **i32), torch.empty(max(n, 1), **i32),
+                torch.empty(max(n * ps.max_runs, 1), **i32), torch.empty(max(ns, 1), **i32),
+                torch.empty(max(ns, 1), **i32), torch.empty(max(ns * ps.max_rows, 1), **i32),
+                torch.empty(max(ns * ps.max_rows, 1), dtype=torch.float64, device=dev))
+    pa = pk.struct()
+    check(lib.cutcell_pack_fill(ctypes.byref(s), st.dim, ctypes.byref(arr), ctypes.byref(ps), ctypes.byref(pa),
+                                _ptr(ws), nbytes, _stream(stream)), "cutcell_pack_fill", allow_flagged=False)
+    return pk
+
+
+def apply_packed(st: Stencils, pk: Packed, phi: torch.Tensor, lphi: torch.Tensor | None = None,
+                 flux: torch.Tensor | None = None, stream=None):
+    """apply() on the compressed stencils: the same (lphi, flux), bit for bit."""
+    s = st.sizes
+    _check_f64(phi, s.n_phi, "phi")
+    if lphi is None:
+        lphi = torch.empty(max(s.n_vol, 1), dtype=torch.float64, device=phi.device)
+    if flux is None:
+        flux = torch.empty(max(s.n_face, 1), dtype=torch.float64, device=phi.device)
+    arr, pa = st.struct(), pk.struct()
+    rc = load().cutcell_apply_packed(ctypes.byref(s), st.dim, ctypes.byref(arr), ctypes.byref(pk.sizes),
+                                     ctypes.byref(pa), _ptr(phi), _ptr(lphi), _ptr(flux), _stream(stream))
+    check(rc, "cutcell_apply_packed", allow_flagged=False)
     return lphi[: s.n_vol], flux[: s.n_face]
 
 

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcutcell.so")
 SOURCES = ["api.hip", "enumerate.hip", "stencil.hip", "stencil_d2q2.hip", "stencil_d2q4.hip", "stencil_d3q2.hip",
            "stencil_d3q4.hip", "stencil_d3q4_mid.hip", "stencil_d3q4_high.hip",
-           "stencil_qr.hip", "apply.hip", "adjoint.hip", "solve.hip", "laplacian.hip", "order.hip"]
+           "stencil_qr.hip", "apply.hip", "adjoint.hip", "solve.hip", "laplacian.hip", "order.hip", "packed.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

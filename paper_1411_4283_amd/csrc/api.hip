@@ -409,6 +409,13 @@ static int build_common(const cutcell_geom* geoms, int32_t n_geom, const cutcell
   timer.mark();
   rc = volume_tables(w, *opts, P.n_vol, out->vol_face, out->vol_scale, st);
   if (rc) return rc;
+  if (out->tmpl && P.n_face > 0) {   // each face's template, -1 where it was solved itself
+    if (opts->reuse_templates)
+      CC_HIP(hipMemcpyAsync(out->tmpl, w.tmpl, sizeof(int32_t) * P.n_face, hipMemcpyDeviceToDevice, st));
+    else
+      hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((P.n_face + 255) / 256)), dim3(256), 0, st, out->tmpl, P.n_face,
+                         -1);
+  }
   timer.mark();
   const size_t ob = sizeof(int64_t) * (n_geom + 1);
   CC_HIP(hipMemcpyAsync(out->phi_off, w.offs, ob, hipMemcpyDeviceToDevice, st));
@@ -482,6 +489,84 @@ int cutcell_apply(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencil
 size_t cutcell_solve_workspace_bytes(const cutcell_sizes* sizes, int32_t restart) {
   if (!sizes || restart < 1 || restart > 1024 || sizes->n_vol < 0 || sizes->n_phi < 0 || sizes->n_face < 0) return 0;
   return solve_workspace_bytes(sizes->n_vol, sizes->n_phi, sizes->n_face, restart);
+}
+
+size_t cutcell_pack_workspace_bytes(const cutcell_sizes* sizes) {
+  if (!sizes || sizes->n_face < 0 || sizes->n_face >= (1LL << 31)) return 0;
+  return pack_temp_bytes(sizes->n_face);
+}
+
+int cutcell_pack_count(const cutcell_sizes* sizes, const cutcell_stencils* st_, cutcell_packed_sizes* out,
+                       void* workspace, size_t workspace_bytes, cutcell_stream_t stream) {
+  if (!sizes || !out) return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (sizes->n_face < 0 || sizes->n_face >= (1LL << 31)) return fail(CUTCELL_E_INVALID_ARG, "bad sizes");
+  long long np = 0;
+  int ns = 0, mr = 0, mw = 0;
+  if (sizes->n_face > 0) {
+    if (!st_ || !st_->row_ptr || !st_->col || !st_->val || !st_->tmpl || !workspace)
+      return fail(CUTCELL_E_INVALID_ARG, "NULL argument (the stencils need their tmpl array)");
+    const int rc = pack_count(sizes->n_face, st_->row_ptr, st_->col, st_->val, st_->tmpl, (char*)workspace,
+                              workspace_bytes, &np, &ns, &mr, &mw, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  out->n_packed = np;
+  out->n_slot = ns;
+  out->max_runs = mr;
+  out->max_rows = mw;
+  return CUTCELL_OK;
+}
+
+int cutcell_pack_fill(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_,
+                      const cutcell_packed_sizes* psizes, cutcell_packed* out, void* workspace,
+                      size_t workspace_bytes, cutcell_stream_t stream) {
+  if (!sizes || !psizes || !out) return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (sizes->n_face < 0 || sizes->n_face >= (1LL << 31)) return fail(CUTCELL_E_INVALID_ARG, "bad sizes");
+  if (psizes->n_packed < 0 || psizes->n_packed > sizes->n_face)
+    return fail(CUTCELL_E_CAPACITY, "packed sizes do not match these stencils (call cutcell_pack_count first)");
+  if (sizes->n_face == 0) return CUTCELL_OK;
+  if (!st_ || !st_->row_ptr || !st_->col || !st_->val || !st_->tmpl || !workspace || !out->flag || !out->phase)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument (the stencils need their tmpl array)");
+  if (psizes->n_packed > 0 && (!out->face || !out->slot || !out->base))
+    return fail(CUTCELL_E_INVALID_ARG, "packed face arrays are NULL");
+  if (psizes->n_slot > 0 && (!out->slot_face || !out->slot_rows || !out->slot_tab || !out->slot_val))
+    return fail(CUTCELL_E_INVALID_ARG, "slot arrays are NULL");
+  PackedSizes ps{psizes->n_packed, psizes->n_slot, psizes->max_runs, psizes->max_rows};
+  PackedOut o{out->flag, out->phase, out->face, out->slot, out->base, out->slot_face, out->slot_rows, out->slot_tab,
+              out->slot_val};
+  return pack_fill(dim, sizes->n_face, st_->row_ptr, st_->col, st_->val, st_->tmpl, (char*)workspace,
+                   workspace_bytes, ps, o, (hipStream_t)stream);
+}
+
+int cutcell_apply_packed(const cutcell_sizes* sizes, int32_t dim, const cutcell_stencils* st_,
+                         const cutcell_packed_sizes* psizes, const cutcell_packed* pk, const double* phi, double* lphi,
+                         double* flux, cutcell_stream_t stream) {
+  if (!sizes || !psizes) return fail(CUTCELL_E_INVALID_ARG, "sizes is NULL");
+  if (dim != 2 && dim != 3) return fail(CUTCELL_E_UNSUPPORTED, "dim must be 2 or 3");
+  if (sizes->n_vol == 0 && sizes->n_face == 0) return CUTCELL_OK;   // nothing to apply (arrays may be NULL)
+  if (!st_ || !phi || !lphi || !flux || !pk || !pk->flag || !pk->phase)
+    return fail(CUTCELL_E_INVALID_ARG, "NULL argument");
+  if (!st_->row_ptr || !st_->col || !st_->val || !st_->vol_face || !st_->vol_scale)
+    return fail(CUTCELL_E_INVALID_ARG, "stencil arrays are NULL");
+  if (psizes->n_packed < 0 || psizes->n_packed > sizes->n_face ||
+      (psizes->n_packed > 0 && (!pk->face || !pk->slot || !pk->base || !pk->slot_rows || !pk->slot_tab ||
+                                !pk->slot_val || psizes->max_runs < 1 || psizes->max_rows < 1 || psizes->n_slot < 1)))
+    return fail(CUTCELL_E_INVALID_ARG, "packed arrays or sizes are inconsistent");
+  PackedArgs a;
+  a.n_packed = psizes->n_packed;
+  a.n_slot = psizes->n_slot;
+  a.max_runs = psizes->max_runs;
+  a.max_rows = psizes->max_rows;
+  a.flag = pk->flag;
+  a.phase = pk->phase;
+  a.face = pk->face;
+  a.slot = pk->slot;
+  a.base = pk->base;
+  a.slot_rows = pk->slot_rows;
+  a.slot_tab = pk->slot_tab;
+  a.slot_val = pk->slot_val;
+  return apply_packed(dim, sizes->n_face, sizes->n_vol, st_->row_ptr, st_->col, st_->val, st_->vol_face,
+                      st_->vol_scale, a, phi, lphi, flux, (hipStream_t)stream);
 }
 
 size_t cutcell_laplacian_workspace_bytes(const cutcell_sizes* sizes) {

@@ -27,35 +27,46 @@ __global__ __launch_bounds__(256) void k_divergence(long long n_vol, const int32
   lphi[v] = vol_scale[v] * s;
 }
 
+int flux_faces(int D, long long n_face, const int64_t* row_ptr, const int32_t* col, const double* val,
+               const double* phi, double* flux, hipStream_t st) {
+  if (n_face <= 0) return CUTCELL_OK;
+  // faces per wave and rounds: about 88 rows per face in 3D order 4, 20-35 in 2D
+  const int T = 256;
+  if (D == 3) {
+    constexpr int F = kFluxFaces3, U = kFluxRounds3;
+    const long long waves = (n_face + F - 1) / F;
+    hipLaunchKernelGGL((k_flux<F, U>), dim3((unsigned)((waves * 64 + T - 1) / T)), dim3(T), 0, st, n_face, row_ptr,
+                       col, val, phi, flux);
+  } else {
+    constexpr int F = kFluxFaces2, U = kFluxRounds2;
+    const long long waves = (n_face + F - 1) / F;
+    hipLaunchKernelGGL((k_flux<F, U>), dim3((unsigned)((waves * 64 + T - 1) / T)), dim3(T), 0, st, n_face, row_ptr,
+                       col, val, phi, flux);
+  }
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
+int divergence(int D, long long n_vol, const int32_t* vol_face, const double* vol_scale, const double* flux,
+               double* lphi, hipStream_t st) {
+  if (n_vol <= 0) return CUTCELL_OK;
+  if (D == 3)
+    hipLaunchKernelGGL(k_divergence<3>, dim3((unsigned)((n_vol + 255) / 256)), dim3(256), 0, st, n_vol, vol_face,
+                       vol_scale, flux, lphi);
+  else
+    hipLaunchKernelGGL(k_divergence<2>, dim3((unsigned)((n_vol + 255) / 256)), dim3(256), 0, st, n_vol, vol_face,
+                       vol_scale, flux, lphi);
+  CC_HIP(hipGetLastError());
+  return CUTCELL_OK;
+}
+
 int apply_operator(int D, long long n_face, long long n_vol, const int64_t* row_ptr, const int32_t* col,
                    const double* val, const int32_t* vol_face, const double* vol_scale, const double* phi,
                    double* lphi, double* flux, double* flux_tmp, hipStream_t st) {
   (void)flux_tmp;
-  if (n_face > 0) {
-    // faces per wave and rounds: about 88 rows per face in 3D order 4, 20-35 in 2D
-    const int T = 256;
-    if (D == 3) {
-      constexpr int F = 4, U = 6;
-      const long long waves = (n_face + F - 1) / F;
-      hipLaunchKernelGGL((k_flux<F, U>), dim3((unsigned)((waves * 64 + T - 1) / T)), dim3(T), 0, st, n_face, row_ptr,
-                         col, val, phi, flux);
-    } else {
-      constexpr int F = 8, U = 4;
-      const long long waves = (n_face + F - 1) / F;
-      hipLaunchKernelGGL((k_flux<F, U>), dim3((unsigned)((waves * 64 + T - 1) / T)), dim3(T), 0, st, n_face, row_ptr,
-                         col, val, phi, flux);
-    }
-  }
-  if (n_vol > 0) {
-    if (D == 3)
-      hipLaunchKernelGGL(k_divergence<3>, dim3((unsigned)((n_vol + 255) / 256)), dim3(256), 0, st, n_vol, vol_face,
-                         vol_scale, flux, lphi);
-    else
-      hipLaunchKernelGGL(k_divergence<2>, dim3((unsigned)((n_vol + 255) / 256)), dim3(256), 0, st, n_vol, vol_face,
-                         vol_scale, flux, lphi);
-  }
-  CC_HIP(hipGetLastError());
-  return CUTCELL_OK;
+  int rc = flux_faces(D, n_face, row_ptr, col, val, phi, flux, st);
+  if (rc) return rc;
+  return divergence(D, n_vol, vol_face, vol_scale, flux, lphi, st);
 }
 
 }  // namespace cutcell

@@ -171,10 +171,55 @@ int apply_adjoint(int D, long long n_face, long long n_vol, long long n_phi, con
                   const int32_t* col, const double* val, const int32_t* vol_face, const double* vol_scale,
                   const Transpose& tr, const double* phi, const double* flux, const double* lbar, double* phi_bar,
                   double* val_bar, double* scale_bar, double* fbar, hipStream_t st);
-// operator apply (Sec. 2.2, Sec. 3.3)
+// operator apply (Sec. 2.2, Sec. 3.3): face fluxes, their divergence, and both
+constexpr int kFluxFaces3 = 4, kFluxRounds3 = 6;   // faces per wave and rounds of the CSR flux pass, 3D
+constexpr int kFluxFaces2 = 8, kFluxRounds2 = 4;   // and 2D
+int flux_faces(int D, long long n_face, const int64_t* row_ptr, const int32_t* col, const double* val,
+               const double* phi, double* flux, hipStream_t st);
+int divergence(int D, long long n_vol, const int32_t* vol_face, const double* vol_scale, const double* flux,
+               double* lphi, hipStream_t st);
 int apply_operator(int D, long long n_face, long long n_vol, const int64_t* row_ptr, const int32_t* col,
                    const double* val, const int32_t* vol_face, const double* vol_scale, const double* phi,
                    double* lphi, double* flux, double* flux_tmp, hipStream_t st);
+
+// the compressed form of the stencils (packed.hip)
+struct PackedSizes {
+  long long n_packed;
+  int n_slot, max_runs, max_rows;
+};
+struct PackedOut {          // the arrays pack_fill writes
+  uint8_t* flag;            // [n_face] 1: the face is packed
+  uint8_t* phase;           // [n_face] lane of its first entry in the CSR flux pass
+  int32_t* face;            // [n_packed]
+  int32_t* slot;            // [n_packed]
+  int32_t* base;            // [n_packed][max_runs]
+  int32_t* slot_face;       // [n_slot]
+  int32_t* slot_rows;       // [n_slot]
+  int32_t* slot_tab;        // [n_slot][max_rows]
+  double* slot_val;         // [n_slot][max_rows]
+};
+struct PackedArgs {         // what the apply reads
+  long long n_packed;
+  int n_slot, max_runs, max_rows;
+  const uint8_t* flag;
+  const uint8_t* phase;
+  const int32_t* face;
+  const int32_t* slot;
+  const int32_t* base;
+  const int32_t* slot_rows;
+  const int32_t* slot_tab;
+  const double* slot_val;
+};
+size_t pack_temp_bytes(long long n_face);
+int pack_count(long long n_face, const int64_t* row_ptr, const int32_t* col, const double* val,
+               const int32_t* tmpl, char* ws, size_t ws_bytes, long long* n_packed, int* n_slot, int* max_runs,
+               int* max_rows, hipStream_t st);
+int pack_fill(int D, long long n_face, const int64_t* row_ptr, const int32_t* col, const double* val,
+              const int32_t* tmpl, char* ws, size_t ws_bytes, const PackedSizes& ps, const PackedOut& out,
+              hipStream_t st);
+int apply_packed(int D, long long n_face, long long n_vol, const int64_t* row_ptr, const int32_t* col,
+                 const double* val, const int32_t* vol_face, const double* vol_scale, const PackedArgs& pk,
+                 const double* phi, double* lphi, double* flux, hipStream_t st);
 
 __global__ void k_fill_i32(int32_t* p, long long n, int32_t v);
 __global__ void k_fill_f64(double* p, long long n, double v);

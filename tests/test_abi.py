@@ -31,7 +31,8 @@ def test_header_declares_the_entry_points():
               "cutcell_build_transpose", "cutcell_transpose_workspace_bytes", "cutcell_backward_workspace_bytes",
               "cutcell_solve", "cutcell_solve_workspace_bytes", "cutcell_laplacian_count", "cutcell_laplacian_fill",
               "cutcell_apply_laplacian", "cutcell_laplacian_workspace_bytes", "cutcell_last_reused_faces", "cutcell_last_qr_faces",
-              "cutcell_ritz", "cutcell_ritz_workspace_bytes", "cutcell_hessenberg_eigs"):
+              "cutcell_ritz", "cutcell_ritz_workspace_bytes", "cutcell_hessenberg_eigs", "cutcell_pack_count",
+              "cutcell_pack_fill", "cutcell_apply_packed", "cutcell_pack_workspace_bytes"):
         assert n in names
 
 
@@ -42,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.cutcell_abi_version() == 11
+    assert lib.cutcell_abi_version() == 12
 
 
 def _opts(**kw):
