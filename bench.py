@@ -125,6 +125,11 @@ def c4_shapes(w):
     return cg.perturbed_spheres(w["n_geom"], w["seed"])
 
 
+SCHEDULE_NOTE = ("per row-count bin (16 rows each): (XCD chunks, persistent workgroups per XCD or 0 for one per "
+                 "face, split mode: 0 parts at their own narrower widths, 1 whole bin at its width, 2 part 0 "
+                 "narrower, 3 parts 0-1 at width - 4), chosen by timing on the workload")
+
+
 def batched_comparison(steps):
     """C4: all faces of 64 perturbed geometries in one build call (one launch per row-count
     bin across every geometry, autotuned schedule) versus one build call per geometry.
@@ -173,13 +178,13 @@ def batched_comparison(steps):
     for r in ref:
         assert torch.equal(st.val[off: off + r.numel()], r), "batched stencils differ from per-geometry ones"
         off += r.numel()
-    sched = [(int(tuning.xcd_chunks[b]), int(tuning.blocks_per_xcd[b])) for b in range(8)]
+    sched = [(int(tuning.xcd_chunks[b]), int(tuning.blocks_per_xcd[b]), int(tuning.split[b])) for b in range(8)]
     out = {"workload": w["desc"], "n_geom": len(dgs), "n_face": int(n_face), "nnz": int(nnz),
            "per_geometry_ms": ms_single, "batched_ms": ms_batch, "batched_autotuned_ms": ms_tuned,
            "per_geometry_faces_per_s": n_face / (ms_single * 1e-3),
            "batched_autotuned_faces_per_s": n_face / (ms_tuned * 1e-3),
            "speedup_vs_per_geometry": ms_single / ms_tuned,
-           "schedule_per_bin": sched, "bin_best_ms": best}
+           "schedule_per_bin": sched, "schedule_note": SCHEDULE_NOTE, "bin_best_ms": best}
     del st, bb, dgs
     torch.cuda.empty_cache()
     return out
@@ -712,8 +717,9 @@ def main():
     schedule = None
     if not args.no_autotune:
         tuning, best = b.autotune(out=st)
-        schedule = [(int(tuning.xcd_chunks[i]), int(tuning.blocks_per_xcd[i])) for i in range(8)]
-        log(f"autotuned schedule per bin (xcd chunks, blocks per xcd): {schedule}")
+        schedule = [(int(tuning.xcd_chunks[i]), int(tuning.blocks_per_xcd[i]), int(tuning.split[i]))
+                    for i in range(8)]
+        log(f"autotuned per bin (xcd chunks, blocks per xcd, split mode): {schedule}")
 
     for _ in range(args.warmup):
         b.build(out=st)
@@ -808,6 +814,7 @@ def main():
         "build_faces_per_s": s.n_face / (float(np.mean([sum(v for v in p.values() if v > 0) for p in phases])) * 1e-3),
         "phases_ms": {k: float(np.mean([p[k] for p in phases])) for k in phases[0]},
         "schedule_per_bin": schedule,
+        "schedule_note": SCHEDULE_NOTE,
         "faces_regular": regular,
         "faces_regular_note": "faces between two cells whose whole path-radius ball is plain interior volume "
                               "(fixed rows); every face, regular or not, is solved",

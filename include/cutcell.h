@@ -117,19 +117,27 @@ enum {
 
 typedef void* cutcell_stream_t; /* hipStream_t */
 
-/* Launch schedule of the stencil solves, per row-count bin b (faces with
- * 16 b < N <= 16 (b + 1) rows).  Results do not depend on it (every face is solved the
- * same way); only the order in which workgroups take faces does.
+/* Launch schedule and kernel widths of the stencil solves, per row-count bin b (faces
+ * with 16 b < N <= 16 (b + 1) rows).  Results do not depend on it (every face is solved
+ * the same way, padding rows are exact zeros); only the order in which workgroups take
+ * faces, and the kernel width they run at, do.
  *   xcd_chunks[b]     1: faces in bin order over the workgroups; 8: the bin is cut into
  *                     8 contiguous chunks, one per XCD (MI355X deals workgroups to its 8
  *                     XCDs in turn, each with its own L2), so faces that share rows share
  *                     an L2.
  *   blocks_per_xcd[b] 0: one workgroup per face; > 0: a persistent grid of
  *                     xcd_chunks * blocks_per_xcd workgroups that walk their chunk.
+ *   split[b]          which kernel widths take the bin's faces with at most 16 (b+1) - 8
+ *                     rows (part 0) and at most 16 (b+1) - 4 rows (part 1), where such
+ *                     narrower instances are compiled (they hold more waves per CU): 0
+ *                     parts 0 and 1 each at its own width (the default); 1 the whole bin
+ *                     at 16 (b+1) rows; 2 part 0 narrower only; 3 parts 0 and 1 at
+ *                     16 (b+1) - 4.
  * cutcell_autotune fills it by timing candidates on the caller's workload. */
 typedef struct {
   int32_t xcd_chunks[8];
   int32_t blocks_per_xcd[8];
+  int32_t split[8];
 } cutcell_tuning;
 
 typedef struct {
@@ -478,6 +486,11 @@ int cutcell_last_profile(double* ms, int32_t n);
 /* Faces whose stencil the last build on the calling thread copied from a template
  * (cutcell_opts.reuse_templates), 0 without reuse. */
 int64_t cutcell_last_reused_faces(void);
+
+/* Faces of each row-count bin (cutcell_tuning) in the last build on the calling thread
+ * (solved there, not copied from templates) into counts[0 .. n-1]: which bins a tuning
+ * for this workload needs.  Returns the number of bins (8), or CUTCELL_E_INVALID_ARG. */
+int cutcell_last_bin_faces(int64_t* counts, int32_t n);
 
 /* Faces of the last build on the calling thread that the Householder QR path solved
  * (all of them under CUTCELL_FACTOR_QR). */

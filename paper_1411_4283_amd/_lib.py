@@ -15,6 +15,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [
         ("xcd_chunks", ctypes.c_int32 * 8),
         ("blocks_per_xcd", ctypes.c_int32 * 8),
+        ("split", ctypes.c_int32 * 8),
     ]
 
 
@@ -197,6 +198,7 @@ SIGNATURES = {
     "cutcell_last_profile": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.c_int32]),
     "cutcell_last_reused_faces": (ctypes.c_int64, []),
     "cutcell_last_qr_faces": (ctypes.c_int64, []),
+    "cutcell_last_bin_faces": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "cutcell_build_stencils_noalloc": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.c_int32, ctypes.POINTER(Opts),
                                                       ctypes.POINTER(Sizes), ctypes.POINTER(StencilArrays), P]),
     "cutcell_last_error": (ctypes.c_char_p, []),

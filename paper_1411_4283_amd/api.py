@@ -210,6 +210,7 @@ class Builder:
     def __init__(self, geoms, path_radius: int, device="cuda", eb_bc: str = "dirichlet",
                  reuse_templates: bool = False, weight_power: float | None = None, factorization: str = "auto"):
         geoms = list(geoms) if isinstance(geoms, (list, tuple)) else [geoms]
+        self.tuned_from_cache = False   # the last autotune took every bin from its cache
         g0 = geoms[0]
         for g in geoms:
             assert (g.dim, g.n, g.h, g.order) == (g0.dim, g0.n, g0.h, g0.order), "a batch shares its grid"
@@ -233,13 +234,26 @@ class Builder:
         self.tuning = tuning
         self.opts.tuning = ctypes.pointer(tuning) if tuning is not None else None
 
-    def autotune(self, out: "Stencils | None" = None, reps: int = 2, stream=None):
-        """Time the candidate schedules of every row-count bin on these geometries, keep the
-        fastest (set_tuning) and return (tuning, best ms per bin).  `out` receives the
-        stencils, as from build()."""
+    def autotune(self, out: "Stencils | None" = None, reps: int = 2, stream=None, cache: str | None = None):
+        """Time the candidate launch schedules and kernel widths of every row-count bin on
+        these geometries, keep the fastest (set_tuning) and return (tuning, best ms per bin).
+        `out` receives the stencils, as from build().
+
+        With `cache` (a JSON file), each bin's choice is kept under the key (GPU
+        architecture, D, Q, path radius, bin): when every bin this workload fills has an
+        entry, those are used without timing (best ms then -1, and self.tuned_from_cache is
+        True); otherwise every bin is timed and the file gets the new entries."""
         if self.sizes is None:
             self.query(stream)
         out = self.allocate() if out is None else out
+        self.tuned_from_cache = False
+        if cache is not None:
+            t = self._tuning_from_cache(cache, out, stream)
+            if t is not None:
+                self.tuned_from_cache = True
+                self.set_tuning(t)
+                self.build(out=out, stream=stream)
+                return t, [-1.0] * 8
         t = Tuning()
         best = (ctypes.c_double * 8)()
         arr = out.struct()
@@ -248,7 +262,32 @@ class Builder:
                                      ctypes.byref(t), best, _stream(stream))
         out.code = check(rc, "cutcell_autotune")
         self.set_tuning(t)
-        return t, [best[i] for i in range(8)]
+        best_ms = [best[i] for i in range(8)]
+        if cache is not None:
+            _cache_store(cache, self._cache_prefix(), t, best_ms)
+        return t, best_ms
+
+    def _cache_prefix(self) -> str:
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        return f"{arch}/D{self.dim}/Q{self.opts.order}/R{self.opts.path_radius}"
+
+    def _tuning_from_cache(self, path: str, out: "Stencils", stream) -> "Tuning | None":
+        entries = _cache_load(path)
+        if not entries:
+            return None
+        self.set_tuning(None)
+        self.build(out=out, stream=stream)   # which bins this workload fills
+        counts = (ctypes.c_int64 * 8)()
+        load().cutcell_last_bin_faces(counts, 8)
+        t = Tuning()
+        prefix = self._cache_prefix()
+        for b in range(8):
+            e = entries.get(f"{prefix}/bin{b}")
+            if counts[b] > 0 and e is None:
+                return None
+            if e is not None:
+                t.xcd_chunks[b], t.blocks_per_xcd[b], t.split[b] = e["xcd_chunks"], e["blocks_per_xcd"], e["split"]
+        return t
 
     def query(self, stream=None) -> Sizes:
         sizes = Sizes()
@@ -322,6 +361,33 @@ class Builder:
                                            garr, _ptr(wb), _ptr(ws), ws.numel(), _stream(stream))
         check(rc, "cutcell_stencils_backward", allow_flagged=False)
         return out, (None if wb is None else wb[: s.nnz])
+
+
+def _cache_load(path: str) -> dict:
+    import json
+    import os
+
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _cache_store(path: str, prefix: str, t: Tuning, best_ms: list) -> None:
+    """Merge the tuned bins (those with a time) into the JSON cache, written atomically."""
+    import json
+    import os
+
+    entries = _cache_load(path)
+    for b in range(8):
+        if best_ms[b] >= 0:
+            entries[f"{prefix}/bin{b}"] = {"xcd_chunks": int(t.xcd_chunks[b]),
+                                           "blocks_per_xcd": int(t.blocks_per_xcd[b]), "split": int(t.split[b]),
+                                           "best_ms": float(best_ms[b])}
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as fh:
+        json.dump(entries, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def build_stencils(geoms, path_radius: int, stream=None, eb_bc: str = "dirichlet") -> Stencils:

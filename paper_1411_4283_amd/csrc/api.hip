@@ -19,6 +19,7 @@ static thread_local bool g_profiling = false;
 static thread_local double g_phase_ms[kPhases] = {-1, -1, -1, -1, -1, -1};
 static thread_local int64_t g_last_reused = 0;
 static thread_local int64_t g_last_qr = 0;
+static thread_local int64_t g_last_bins[kMaxBins] = {0, 0, 0, 0, 0, 0, 0, 0};
 
 struct PhaseTimer {
   hipEvent_t ev[kPhases + 1];
@@ -397,6 +398,7 @@ static int build_common(const cutcell_geom* geoms, int32_t n_geom, const cutcell
   CC_HIP(hipMemcpyAsync(bc, w.bins, sizeof(bc), hipMemcpyDeviceToHost, st));
   CC_HIP(hipStreamSynchronize(st));
   g_last_reused = bc[kMaxBins + 1];
+  for (int b = 0; b < kMaxBins; ++b) g_last_bins[b] = bc[b];
   if (tune_out) {
     double bm[kMaxBins];
     rc = tune_stencils(w, *opts, bc, out->row_ptr, out->col, out->val, out->status, st, tune_out, reps, bm);
@@ -465,6 +467,12 @@ int cutcell_autotune(const cutcell_geom* geoms, int32_t n_geom, const cutcell_op
 void cutcell_set_profiling(int enable) { g_profiling = enable != 0; }
 
 int64_t cutcell_last_reused_faces(void) { return g_last_reused; }
+
+int cutcell_last_bin_faces(int64_t* counts, int32_t n) {
+  if (!counts || n < 0) return fail(CUTCELL_E_INVALID_ARG, "counts is NULL");
+  for (int b = 0; b < n && b < kMaxBins; ++b) counts[b] = g_last_bins[b];
+  return kMaxBins;
+}
 
 int64_t cutcell_last_qr_faces(void) { return g_last_qr; }
 

@@ -134,6 +134,7 @@ static void schedules_from(const cutcell_tuning* t, BinSchedule* sc) {
     if (t) {
       sc[b].xcd = t->xcd_chunks[b] > 1 ? t->xcd_chunks[b] : 1;
       sc[b].per_xcd = t->blocks_per_xcd[b] > 0 ? t->blocks_per_xcd[b] : 0;
+      sc[b].split = (t->split[b] >= 0 && t->split[b] <= 3) ? t->split[b] : 0;
     }
   }
 }
@@ -153,8 +154,9 @@ int backward_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_c
   return run_bins(w, o, bin_count, row_ptr, col, nullptr, nullptr, st, &bw, sc);
 }
 
-// Times every candidate schedule of every non-empty bin on these faces (HIP events, best
-// of `reps`) and keeps the fastest; then solves all bins with the chosen schedules, so
+// Times every candidate of every non-empty bin on these faces (HIP events, best of
+// `reps`) and keeps the fastest: the five launch schedules, crossed with the split modes
+// the bin's compiled kernel widths allow; then solves all bins with the choices, so
 // val/status hold the same stencils as an untuned build.
 int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count, const int64_t* row_ptr,
                   const int32_t* col, double* val, int8_t* status, hipStream_t st, cutcell_tuning* out, int reps,
@@ -164,8 +166,8 @@ int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count
   CC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const int X = kXcds;
   const int resident = std::max(1, cus / X) * 4;   // workgroups per XCD at one wave per SIMD
-  const BinSchedule cand[] = {{1, 0}, {X, 0}, {X, resident}, {X, 2 * resident}, {1, X * resident}};
-  const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+  const BinSchedule launch[] = {{1, 0}, {X, 0}, {X, resident}, {X, 2 * resident}, {1, X * resident}};
+  const int nlaunch = (int)(sizeof(launch) / sizeof(launch[0]));
   hipEvent_t e0, e1;
   CC_HIP(hipEventCreate(&e0));
   CC_HIP(hipEventCreate(&e1));
@@ -175,9 +177,19 @@ int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count
     best_ms[b] = -1.0;
     if (bin_count[b] == 0) continue;
     double best = 1e300;
-    for (int c = 0; c < ncand; ++c) {
+    // split modes that differ for this bin: 1 (whole bin at its width) always; 2 with a
+    // NPAD - 8 instance, 3 with a NPAD - 4 one, 0 with both
+    const int nm = narrow_mask_of(o.dim, o.order, b);
+    int splits[4], nsplit = 0;
+    splits[nsplit++] = 1;
+    if (nm & 1) splits[nsplit++] = 2;
+    if (nm & 2) splits[nsplit++] = 3;
+    if ((nm & 3) == 3) splits[nsplit++] = 0;
+    for (int c = 0; c < nlaunch * nsplit; ++c) {
+      BinSchedule cand = launch[c % nlaunch];
+      cand.split = splits[c / nlaunch];
       BinSchedule trial[kMaxBins];
-      for (int i = 0; i < kMaxBins; ++i) trial[i] = cand[c];
+      for (int i = 0; i < kMaxBins; ++i) trial[i] = cand;
       double tmin = 1e300;
       for (int r = 0; r < reps; ++r) {
         CC_HIP(hipEventRecord(e0, st));
@@ -191,7 +203,7 @@ int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count
       }
       if (tmin < best) {
         best = tmin;
-        sc[b] = cand[c];
+        sc[b] = cand;
       }
     }
     best_ms[b] = best;
@@ -201,6 +213,7 @@ int tune_stencils(const Work& w, const cutcell_opts& o, const int32_t* bin_count
   for (int b = 0; b < kMaxBins; ++b) {
     out->xcd_chunks[b] = sc[b].xcd;
     out->blocks_per_xcd[b] = sc[b].per_xcd;
+    out->split[b] = sc[b].split;
   }
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.flagged, 1LL, 0);
   return run_bins(w, o, bin_count, row_ptr, col, val, status, st, nullptr, sc);

@@ -948,10 +948,15 @@ inline StencilArgs stencil_args(const Work& w, double hscale, const int32_t* per
 }
 
 // Launch shape of one bin: xcd = 1 or the number of XCDs whose chunks the bin is split
-// into; per_xcd = 0 for one workgroup per face, else the persistent workgroups per chunk.
+// into; per_xcd = 0 for one workgroup per face, else the persistent workgroups per chunk;
+// split: which kernel widths take the bin's parts 0 and 1 (its faces with at most
+// NPAD - 8 and NPAD - 4 rows) where narrower instances are compiled -- 0: part 0 at
+// NPAD - 8 and part 1 at NPAD - 4; 1: none, the whole bin at NPAD rows; 2: part 0 at
+// NPAD - 8 only; 3: parts 0 and 1 at NPAD - 4.
 struct BinSchedule {
   int xcd = 1;
   int per_xcd = 0;
+  int split = 0;
   bool route = true;   // faces the Gram path cannot resolve go to the QR path
 };
 
@@ -1018,16 +1023,49 @@ void launch_row_bin(const Work& w, double hscale, const int32_t* perm, long long
   long long done = 0;
   if (!bw) {
     if constexpr (narrower_pays<D, Q, P0, NPAD>()) {
-      launch_bin<D, Q, P0, true>(w, hscale, perm, n0, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
-      done = n0;
+      if (sc.split == 0 || sc.split == 2) {
+        launch_bin<D, Q, P0, true>(w, hscale, perm, n0, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
+        done = n0;
+      }
     }
     if constexpr (narrower_pays<D, Q, P1, NPAD>()) {
-      launch_bin<D, Q, P1, true>(w, hscale, perm + done, n0 + n1 - done, row_ptr, col, val, status, st, bw, sc, neu,
-                                 h, wpow);
-      done = n0 + n1;
+      if (sc.split == 0 || sc.split == 3) {
+        launch_bin<D, Q, P1, true>(w, hscale, perm + done, n0 + n1 - done, row_ptr, col, val, status, st, bw, sc,
+                                   neu, h, wpow);
+        done = n0 + n1;
+      }
     }
   }
   launch_bin<D, Q, NPAD>(w, hscale, perm + done, nbin - done, row_ptr, col, val, status, st, bw, sc, neu, h, wpow);
+}
+
+// Narrower instances compiled for the bin of NPAD rows: bit 0 for NPAD - 8, bit 1 for NPAD - 4.
+template <int D, int Q, int NPAD>
+constexpr int narrow_mask() {
+  return (narrower_pays<D, Q, NPAD - kBinRows / 2, NPAD>() ? 1 : 0) |
+         (narrower_pays<D, Q, NPAD - kBinRows / 4, NPAD>() ? 2 : 0);
+}
+
+// the same for dimension, order and bin b known at run time (the split modes to tune)
+inline int narrow_mask_of(int D, int Q, int b) {
+  auto pick = [&](auto DD, auto QQ) {
+    constexpr int Dc = decltype(DD)::value, Qc = decltype(QQ)::value;
+    switch (b) {
+      case 1: return narrow_mask<Dc, Qc, 32>();
+      case 2: return narrow_mask<Dc, Qc, 48>();
+      case 3: return narrow_mask<Dc, Qc, 64>();
+      case 4: return narrow_mask<Dc, Qc, 80>();
+      case 5: return narrow_mask<Dc, Qc, 96>();
+      case 6: return narrow_mask<Dc, Qc, 112>();
+      case 7: return narrow_mask<Dc, Qc, 128>();
+      default: return 0;
+    }
+  };
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I4 = std::integral_constant<int, 4>;
+  if (D == 2) return Q == 2 ? pick(I2{}, I2{}) : pick(I2{}, I4{});
+  return Q == 2 ? pick(I3{}, I2{}) : pick(I3{}, I4{});
 }
 
 // Explicit instantiations: each (dimension, order, bin) lives in one stencil_d*q*.hip file,

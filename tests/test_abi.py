@@ -32,7 +32,7 @@ def test_header_declares_the_entry_points():
               "cutcell_solve", "cutcell_solve_workspace_bytes", "cutcell_laplacian_count", "cutcell_laplacian_fill",
               "cutcell_apply_laplacian", "cutcell_laplacian_workspace_bytes", "cutcell_last_reused_faces", "cutcell_last_qr_faces",
               "cutcell_ritz", "cutcell_ritz_workspace_bytes", "cutcell_hessenberg_eigs", "cutcell_pack_count",
-              "cutcell_pack_fill", "cutcell_apply_packed", "cutcell_pack_workspace_bytes"):
+              "cutcell_pack_fill", "cutcell_apply_packed", "cutcell_pack_workspace_bytes", "cutcell_last_bin_faces"):
         assert n in names
 
 

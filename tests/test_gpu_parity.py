@@ -369,22 +369,49 @@ def test_every_schedule_gives_identical_stencils():
     g = cg.make_geometry(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 24, 4)
     dg, b, st0 = _gpu_build(g, 3)
     val0, status0 = st0.val.clone(), st0.status.clone()
-    for xcd, per in [(8, 0), (8, 16), (8, 100), (1, 64), (3, 5)]:
+    for xcd, per, split in [(8, 0, 0), (8, 16, 1), (8, 100, 2), (1, 64, 3), (3, 5, 1), (1, 0, 2)]:
         t = Tuning()
         for i in range(8):
-            t.xcd_chunks[i], t.blocks_per_xcd[i] = xcd, per
+            t.xcd_chunks[i], t.blocks_per_xcd[i], t.split[i] = xcd, per, split
         b.set_tuning(t)
-        _say(f"schedule xcd={xcd} per={per}")
+        _say(f"schedule xcd={xcd} per={per} split={split}")
         st = b.build()
         torch.cuda.synchronize()
-        assert torch.equal(st.val, val0) and torch.equal(st.status, status0), (xcd, per)
+        assert torch.equal(st.val, val0) and torch.equal(st.status, status0), (xcd, per, split)
     b.set_tuning(None)
     tuning, best = b.autotune()
     st = b.build()
     torch.cuda.synchronize()
-    _say(f"autotuned {[(tuning.xcd_chunks[i], tuning.blocks_per_xcd[i]) for i in range(8)]} best {best}")
+    _say(f"autotuned {[(tuning.xcd_chunks[i], tuning.blocks_per_xcd[i], tuning.split[i]) for i in range(8)]} "
+         f"best {best}")
     assert torch.equal(st.val, val0) and torch.equal(st.status, status0)
     assert any(x > 0 for x in best)
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The JSON cache: a first autotune times every bin and stores each filled bin under
+    (arch, D, Q, R, bin); a second one, on another builder of the same shape, takes those
+    entries without timing and builds the same stencils."""
+    import json
+
+    g = cg.make_geometry(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 24, 4)
+    dg, b, st0 = _gpu_build(g, 3)
+    path = str(tmp_path / "tuning.json")
+    t1, best1 = b.autotune(cache=path)
+    assert not b.tuned_from_cache
+    entries = json.load(open(path))
+    filled = [i for i in range(8) if best1[i] >= 0]
+    assert filled and all(any(k.endswith(f"/D3/Q4/R3/bin{i}") for k in entries) for i in filled)
+    b2 = cc.Builder(dg, 3)
+    t2, best2 = b2.autotune(cache=path)
+    assert b2.tuned_from_cache and best2 == [-1.0] * 8
+    for i in filled:
+        assert (t2.xcd_chunks[i], t2.blocks_per_xcd[i], t2.split[i]) == (t1.xcd_chunks[i], t1.blocks_per_xcd[i],
+                                                                          t1.split[i])
+    st = b2.build()
+    torch.cuda.synchronize()
+    assert torch.equal(st.val, st0.val) and torch.equal(st.status, st0.status)
+    _say(f"cache: {len(entries)} entries, bins {filled} reused")
 
 
 def test_star256_order4_full_size():
