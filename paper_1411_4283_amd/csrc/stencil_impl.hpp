@@ -49,9 +49,11 @@ constexpr double kRankTol = 1e-12;       // rank deficiency: min |R_kk| <= kRank
 constexpr double kCondRoute = 3e4;
 constexpr double kSmallCell = 1e-3;      // rows (and EB flux vectors) of smaller cells in double-double
 constexpr double kSettleTol = 1e-6;
-// Refinement residuals of faces whose bound on cond(G^) stays below this (cond(B) below
-// about 3e3) are summed in plain FP64: their rounding then moves the stencil by about
-// cond(B) eps < 1e-12 relative, and compensated sums cost ten times the instructions.
+// Faces whose bound on cond(G^) stays below this (cond(B) below about 3e3) refine in
+// plain FP64.  Past it, z = B y and the residuals are summed in compensated arithmetic and
+// z is kept as a double-double: the rounding of an FP64 product B y leaves in z a part
+// outside the range of B, which the residual cannot see and refinement cannot remove,
+// of relative size up to about cond(B) eps (4e-12 at cond(B) = 3e4, the routing bound).
 constexpr double kDot2Cond = 1e7;
 constexpr int kRefine = 1;
 constexpr int kRefineBackward = 2;   // refinement steps of the adjoint's least-squares solve
@@ -72,6 +74,14 @@ __device__ __forceinline__ void dot2_add(Dot2& a, double x, double y) {
   const double q = (a.s - (s - bb)) + (p - bb);
   a.s = s;
   a.c += q + e;
+}
+// a + b as an unevaluated sum s + c
+__device__ __forceinline__ Dot2 dot2_join(Dot2 a, Dot2 b) {
+#pragma clang fp contract(off)
+  const double s = a.s + b.s;
+  const double bb = s - a.s;
+  const double q = (a.s - (s - bb)) + (b.s - bb);
+  return Dot2{s, (a.c + b.c) + q};
 }
 __device__ __forceinline__ double dot2_merge(Dot2 a, Dot2 b) {
 #pragma clang fp contract(off)
@@ -175,7 +185,10 @@ struct LeanSmem {
   static constexpr int MV = GramSplit<D, Q>::MV;
   double Bs[NPAD * MS];      // rows of B = W A~
   union {
-    double zs[NPAD];                   // z = B y (refinement)
+    struct {
+      double zs[NPAD];                 // z = B y (refinement; the pivot row of the sweep)
+      double zl[NPAD];                 // its low part where z is a double-double
+    };
     double nus[D][M1];                 // EB normal moments about x0 (flux vector)
     double tt[M * (MV > 0 ? MV : 1)];  // trailing Gram columns (transposition)
   };
@@ -193,6 +206,7 @@ struct FaceSmem {
   double gsum[M + 1];        // per-component sums of the adjoint
   double ys[M + 1];          // y = G^-1 F~
   double zs[NPAD];           // z = B y
+  double zl[NPAD];           // its low part where z is a double-double
   double wls[NPAD];          // W
   double nus[D][M1];         // EB normal moments about x0
 };
@@ -506,13 +520,18 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   const bool cond_ok = cbound <= kCondRoute * kCondRoute;
   const bool dot2 = !(cbound <= kDot2Cond);
 
-  // ---- semi-normal solve with one refinement step (compensated residual past kDot2Cond) -------
+  // ---- semi-normal solve with one refinement step (compensated past kDot2Cond) ---------
   // y = G^-1 rhs with G^ = E G E (E = diag(sdiag)):  y = E (-a) (E rhs).  Lane p holds
-  // component p of F~, rhs and y; lane r holds z of its rows r, r + 64.
+  // component p of F~, rhs and y; lane r holds z of its rows r, r + 64 (past kDot2Cond
+  // as zreg + zlo).
   double rhs = fv * sdiag;
   double ysum = 0.0;
   double dlast = 0.0;   // largest change of W z in the refinement step
-  static_for<0, NR>([&](auto R) { zreg[R] = 0.0; });
+  double zlo[NR];
+  static_for<0, NR>([&](auto R) {
+    zreg[R] = 0.0;
+    zlo[R] = 0.0;
+  });
   for (int it = 0; it <= kRefine; ++it) {
     double tq[4] = {0.0, 0.0, 0.0, 0.0};
     static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], readlane_f64(rhs, J), tq[J % 4]); });
@@ -523,29 +542,50 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
       if (r < NPAD) {
-        double sq4[4] = {0.0, 0.0, 0.0, 0.0};
-        static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], readlane_f64(dy, J), sq4[J % 4]); });
-        const double inc = (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
-        zreg[R] += inc;
+        double inc;
+        if (dot2) {
+          Dot2 d0{0.0, 0.0}, d1{0.0, 0.0};
+          static_for<0, M>([&](auto J) {
+            if constexpr (J % 2 == 0) dot2_add(d0, Bs[r * MS + J], readlane_f64(dy, J));
+            else dot2_add(d1, Bs[r * MS + J], readlane_f64(dy, J));
+          });
+          const Dot2 d = dot2_join(d0, d1);
+          dd zs2 = dd_add(dd{zreg[R], zlo[R]}, dd{d.s, d.c});
+          zreg[R] = zs2.hi;
+          zlo[R] = zs2.lo;
+          inc = d.s + d.c;
+        } else {
+          double sq4[4] = {0.0, 0.0, 0.0, 0.0};
+          static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], readlane_f64(dy, J), sq4[J % 4]); });
+          inc = (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
+          zreg[R] += inc;
+        }
         if (it == kRefine) dlast = fmax(dlast, fabs(wreg[R] * inc));
       }
     });
     if (it == kRefine) break;
-    // residual of B^T z = F~ (two interleaved sums, compensated Dot2 ones past kDot2Cond); z goes
-    // through LDS, B^T is read by columns
+    // residual of B^T z = F~ (two interleaved sums, compensated past kDot2Cond, where the
+    // low part of z enters the compensation); z goes through LDS, B^T is read by columns
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
-      if (r < NPAD) sm.zs[r] = zreg[R];
+      if (r < NPAD) {
+        sm.zs[r] = zreg[R];
+        sm.zl[r] = zlo[R];
+      }
     });
     __syncthreads();
     double res = 0.0;
     if (act && dot2) {
       Dot2 d0{fv, 0.0}, d1{0.0, 0.0};
+      double lo = 0.0;
 #pragma unroll 4
       for (int r = 0; r < NPAD; r += 2) {
         dot2_add(d0, -Bs[(r + 0) * MS + lane], sm.zs[r + 0]);
         dot2_add(d1, -Bs[(r + 1) * MS + lane], sm.zs[r + 1]);
+        lo = fma(-Bs[(r + 0) * MS + lane], sm.zl[r + 0], lo);
+        lo = fma(-Bs[(r + 1) * MS + lane], sm.zl[r + 1], lo);
       }
+      d1.c += lo;
       res = dot2_merge(d0, d1);
     } else if (act) {
       double p0 = fv, p1 = 0.0;
@@ -559,6 +599,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     rhs = res * sdiag;
     __syncthreads();
   }
+  if (dot2) static_for<0, NR>([&](auto R) { zreg[R] += zlo[R]; });
   if constexpr (SM::kFull) {
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;

@@ -44,8 +44,9 @@ def _host(st):
             st.status.cpu().numpy()[: s.n_face])
 
 
-def _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g):
-    """Compare the listed faces with the oracle, one by one."""
+def _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g, where=None):
+    """Compare the listed faces with the oracle, one by one; `where` (a list) receives
+    (error, face) of the worst one."""
     worst = 0.0
     for f in faces:
         f = int(f)
@@ -59,6 +60,8 @@ def _check_faces(g, en, R, faces, rp_g, col_g, val_g, st_g):
             continue
         err = np.abs(val_g[a:b] - s).max() / np.abs(s).max()
         assert err <= 1e-11, f"face {f}: rel err {err:.3e}, cond {oracle.face_condition(g, en, f, R):.3e}"
+        if where is not None and err > worst:
+            where[:] = [err, f]
         worst = max(worst, err)
     return worst
 
@@ -215,7 +218,7 @@ def test_batched_perturbed_spheres_against_oracle():
     colb = st.col[: st.sizes.nnz].cpu().numpy()
     valb = st.val[: st.sizes.nnz].cpu().numpy()
     stsb = st.status[: st.sizes.n_face].cpu().numpy()
-    worst_all, conds_all = 0.0, []
+    worst_all, conds_all, worst_at = 0.0, [], None
     for k, g in enumerate(gs):
         en = oracle.enumerate_geometry(g)
         a, e = fo[k], fo[k + 1]
@@ -225,11 +228,16 @@ def test_batched_perturbed_spheres_against_oracle():
         rp_o, _ = oracle.neighbours_all(en, 3)
         assert np.array_equal(rp_g, rp_o)
         faces, conds = _targeted_faces(g, en, 3, np.random.default_rng(100 + k), n_cand=400)
-        worst_all = max(worst_all, _check_faces(g, en, 3, faces, rp_g, col_g, val_g, stsb[a:e]))
+        where = []
+        w = _check_faces(g, en, 3, faces, rp_g, col_g, val_g, stsb[a:e], where)
+        if w > worst_all:
+            worst_all = w
+            worst_at = (k, where[1], oracle.face_condition(g, en, where[1], 3))
         conds_all.append(conds)
     c = np.concatenate(conds_all)
     _say(f"c4: {len(gs)} geometries, {st.sizes.n_face} faces, {st.qr_faces} by QR; candidate cond p50 "
-         f"{np.median(c):.2e} p99 {np.percentile(c, 99):.2e} max {c.max():.2e}; worst rel err {worst_all:.2e}")
+         f"{np.median(c):.2e} p99 {np.percentile(c, 99):.2e} max {c.max():.2e}; worst rel err {worst_all:.2e} "
+         f"(geometry {worst_at[0]}, face {worst_at[1]}, cond {worst_at[2]:.2e})")
 
 
 def test_full_size_faces_of_every_row_count_in_the_split_bin(c3):
