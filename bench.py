@@ -34,7 +34,9 @@ def log(msg):
 
 
 KERNEL_SOURCES = ("paper_1411_4283_amd/csrc/stencil.hip", "paper_1411_4283_amd/csrc/stencil_impl.hpp",
-                  "paper_1411_4283_amd/csrc/rows.hpp",
+                  "paper_1411_4283_amd/csrc/rows.hpp", "paper_1411_4283_amd/csrc/rows_dd.hpp",
+                  "paper_1411_4283_amd/csrc/dd.hpp", "paper_1411_4283_amd/csrc/stencil_qr.hip",
+                  "paper_1411_4283_amd/csrc/stencil_qr.hpp",
                   "paper_1411_4283_amd/csrc/common.hpp", "paper_1411_4283_amd/csrc/kernels.hpp",
                   "paper_1411_4283_amd/csrc/apply.hip", "paper_1411_4283_amd/csrc/gather.hpp")
 TRAFFIC_FILE = "profiles/traffic_3d_order4_sphere64.md"
