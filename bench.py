@@ -181,12 +181,16 @@ def batched_comparison(steps):
         assert torch.equal(st.val[off: off + r.numel()], r), "batched stencils differ from per-geometry ones"
         off += r.numel()
     sched = [(int(tuning.xcd_chunks[b]), int(tuning.blocks_per_xcd[b]), int(tuning.split[b])) for b in range(8)]
+    flagged = int((st.status[: st.sizes.n_face] != 0).sum())
     out = {"workload": w["desc"], "n_geom": len(dgs), "n_face": int(n_face), "nnz": int(nnz),
            "per_geometry_ms": ms_single, "batched_ms": ms_batch, "batched_autotuned_ms": ms_tuned,
            "per_geometry_faces_per_s": n_face / (ms_single * 1e-3),
            "batched_autotuned_faces_per_s": n_face / (ms_tuned * 1e-3),
            "speedup_vs_per_geometry": ms_single / ms_tuned,
-           "schedule_per_bin": sched, "schedule_note": SCHEDULE_NOTE, "bin_best_ms": best}
+           "schedule_per_bin": sched, "schedule_note": SCHEDULE_NOTE, "bin_best_ms": best,
+           "faces_flagged": flagged, "faces_by_qr": int(st.qr_faces),
+           "parity_note": "stencils against the oracle on 8 seeded geometries of this batch (targeted faces): "
+                          "tests/test_gpu_parity.py::test_batched_perturbed_spheres_against_oracle"}
     del st, bb, dgs
     torch.cuda.empty_cache()
     return out

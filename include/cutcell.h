@@ -247,14 +247,14 @@ int cutcell_build_stencils(const cutcell_geom* geoms, int32_t n_geom, const cutc
  * library's own scratch in place of the caller's workspace.  The scratch is one static
  * device array of CUTCELL_STATIC_SCRATCH_BYTES per GPU, held from the library's loading to
  * the end of the process; a batch whose workspace (cutcell_workspace_bytes) is larger is
- * refused with CUTCELL_E_WORKSPACE before any work (160 MiB holds one geometry up to 64^3 at
- * order 4).  The call allocates nothing and records no profiling events.  Every call on one
+ * refused with CUTCELL_E_WORKSPACE before any work (256 MiB holds one geometry up to 64^3 at
+ * order 4, which needs about 198 MiB).  The call allocates nothing and records no profiling events.  Every call on one
  * GPU uses that GPU's array, which keeps the last call's contents (the build clears what it
  * needs), so calls that overlap on one GPU -- other threads, other streams -- race and must
  * be serialised by the caller.  `sizes` comes from cutcell_query (with a workspace of the
  * caller's, e.g. at set-up).  Outputs and return codes as cutcell_build_stencils.
  * Synchronises `stream`. */
-#define CUTCELL_STATIC_SCRATCH_BYTES ((size_t)160 << 20)
+#define CUTCELL_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
 int cutcell_build_stencils_noalloc(const cutcell_geom* geoms, int32_t n_geom, const cutcell_opts* opts,
                                    const cutcell_sizes* sizes, cutcell_stencils* out, cutcell_stream_t stream);
 

@@ -40,7 +40,7 @@ BC_NEUMANN = 1
 FACTOR_AUTO = 0
 FACTOR_QR = 1
 FACTOR_GRAM = 2
-STATIC_SCRATCH_BYTES = 160 << 20   # CUTCELL_STATIC_SCRATCH_BYTES
+STATIC_SCRATCH_BYTES = 256 << 20   # CUTCELL_STATIC_SCRATCH_BYTES
 
 
 class Geom(ctypes.Structure):

@@ -187,3 +187,14 @@ def test_stencil_adjoint_rejects_neumann_on_the_host(lib):
                                        ctypes.byref(tr), 8, None, ctypes.byref(gr), None, 8, 1 << 20, None)
     assert rc == _lib.E_UNSUPPORTED
     assert b"Dirichlet" in lib.cutcell_last_error()
+
+
+def test_one_fourth_order_64_cubed_geometry_fits_the_static_scratch(lib):
+    """The no-allocation build's scratch holds the workspace of one 64^3 order-4 geometry
+    (the header's promise), and a batch of four 48^3 ones exceeds it."""
+    from paper_1411_4283_amd.api import make_opts
+
+    o = make_opts(3, (64, 64, 64), 1 / 64, 4, 3)
+    assert 0 < lib.cutcell_workspace_bytes(ctypes.byref(o), 1) <= _lib.STATIC_SCRATCH_BYTES
+    o48 = make_opts(3, (48, 48, 48), 1 / 48, 4, 3)
+    assert lib.cutcell_workspace_bytes(ctypes.byref(o48), 4) > _lib.STATIC_SCRATCH_BYTES
