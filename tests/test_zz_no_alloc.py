@@ -45,7 +45,9 @@ def _noalloc_build(b):
 @pytest.mark.parametrize("qr", [False, True])
 def test_noalloc_build_matches_the_workspace_build_twice(qr):
     fac = "qr" if qr else "auto"
-    cases = [(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 20, 4, 3), (cg.ball_outside((0.5, 0.5), 0.25), 24, 2, 2)]
+    # the 64^3 fourth-order workload (the largest the scratch promises to hold), then smaller
+    cases = [(cg.ball_outside((0.5, 0.5, 0.5), 0.3), 64, 4, 3), (cg.ball_outside((0.5, 0.5, 0.5), 0.3), 20, 4, 3),
+             (cg.ball_outside((0.5, 0.5), 0.25), 24, 2, 2)]
     for shape, n, Q, R in cases:          # the second call has the smaller input
         g = cg.make_geometry(shape, n, Q)
         dg = cc.DeviceGeometry.from_host(g, DEV)
