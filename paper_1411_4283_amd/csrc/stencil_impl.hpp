@@ -469,31 +469,33 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   // ---- equilibrate to unit diagonal and invert: lane i holds row i ----------------------------
   // Symmetric Gauss-Jordan sweeps over the pivots k = 0..M-1 turn G^ into -G^-1 in place;
   // the pivot of step k is the k-th Schur complement pivot (L_kk^2 of the Cholesky factor),
-  // which gives the rank test.  Lane k's row is the pivot row (= column, by symmetry); the
-  // other lanes read it with v_readlane, so a sweep step touches neither LDS nor a barrier.
+  // which gives the rank and routing tests.  Values that every lane needs from one lane
+  // (the pivot rows, E, the right-hand sides) go through a shared-memory slot per lane and
+  // come back as broadcast loads, in place of v_readlane through scalar registers.
   const bool act = lane < M;
+  double* piv = sm.zs;   // free between the flux vector and the refinement
+  const int pslot = lane < M ? lane : M;   // lanes past M write an unused slot (M < NPAD)
   double gdiag = 1.0;
   static_for<0, M>([&](auto C) { gdiag = (lane == C) ? a[C] : gdiag; });
   sdiag = act ? 1.0 / sqrt(gdiag) : 1.0;
-  static_for<0, M>([&](auto J) { a[J] = act ? a[J] * sdiag * readlane_f64(sdiag, J) : 0.0; });
+  piv[pslot] = sdiag;
+  static_for<0, M>([&](auto J) { a[J] = act ? a[J] * sdiag * piv[J] : 0.0; });
   double gnorm = 0.0;   // ||G^||_inf: largest absolute row sum of the equilibrated Gram matrix
   static_for<0, M>([&](auto J) { gnorm += fabs(a[J]); });
-  double pmax = 0.0, pmin = 1e300;
+  double pmax = 0.0, pmin = 1e300;   // extreme pivots L_kk^2 (the tests square their bounds)
   // Step k:  a_ij -= (a_ik / d) a_kj  (i, j != k);  a_ik /= d;  a_kj /= d;  a_kk = -1/d.
   // Each lane scales its multiplier once (u = a_ik / d; on lane k, 1 - 1/d turns the
   // pivot row into a_kj / d), so every entry is one FMA.  The sweep keeps the matrix
   // symmetric (up to rounding), so the pivot row is the pivot column: every lane stores
   // its entry of column k in shared memory (one store) and all lanes read the row back
-  // with broadcast loads, eight entries at a time before their FMAs -- in place of two
-  // v_readlane per entry through scalar registers (4 % faster on the 64^3 build).
-  double* piv = sm.zs;   // free between the flux vector and the refinement
+  // with broadcast loads, eight entries at a time before their FMAs.
   static_for<0, M>([&](auto K) {
     constexpr int k = K;
-    piv[lane < M ? lane : M] = a[k];   // lanes past M write an unused slot (M < NPAD)
+    piv[pslot] = a[k];
     const double d = piv[k];
-    const double sq = sqrt(d > 0.0 ? d : 0.0);
-    pmax = fmax(pmax, sq);
-    pmin = fmin(pmin, sq);
+    const double dp = d > 0.0 ? d : 0.0;
+    pmax = fmax(pmax, dp);
+    pmin = fmin(pmin, dp);
     const double rd = recip_f64(d);
     const double u = (lane == k) ? 1.0 - rd : a[k] * rd;
     static_for<0, (M + 7) / 8>([&](auto G) {
@@ -509,7 +511,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     });
     a[k] = (lane == k) ? -rd : u;
   });
-  const bool pivots_ok = (pmin > kRouteTol * pmax) && (pmax > 0.0);
+  const bool pivots_ok = (pmin > kRouteTol * kRouteTol * pmax) && (pmax > 0.0);
   double inv2 = 0.0;    // ||G^^-1||_F^2, from the rows of the inverse
   static_for<0, M>([&](auto J) { inv2 = fma(a[J], a[J], inv2); });
   for (int o = 32; o > 0; o >>= 1) {
@@ -534,10 +536,12 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
   });
   for (int it = 0; it <= kRefine; ++it) {
     double tq[4] = {0.0, 0.0, 0.0, 0.0};
-    static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], readlane_f64(rhs, J), tq[J % 4]); });
+    piv[pslot] = rhs;
+    static_for<0, M>([&](auto J) { tq[J % 4] = fma(-a[J], piv[J], tq[J % 4]); });
     const double t = (tq[0] + tq[1]) + (tq[2] + tq[3]);
     const double dy = act ? t * sdiag : 0.0;
     ysum += dy;
+    piv[pslot] = dy;
     // z += B dy
     static_for<0, NR>([&](auto R) {
       const int r = lane + 64 * R;
@@ -546,8 +550,8 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
         if (dot2) {
           Dot2 d0{0.0, 0.0}, d1{0.0, 0.0};
           static_for<0, M>([&](auto J) {
-            if constexpr (J % 2 == 0) dot2_add(d0, Bs[r * MS + J], readlane_f64(dy, J));
-            else dot2_add(d1, Bs[r * MS + J], readlane_f64(dy, J));
+            if constexpr (J % 2 == 0) dot2_add(d0, Bs[r * MS + J], piv[J]);
+            else dot2_add(d1, Bs[r * MS + J], piv[J]);
           });
           const Dot2 d = dot2_join(d0, d1);
           dd zs2 = dd_add(dd{zreg[R], zlo[R]}, dd{d.s, d.c});
@@ -556,7 +560,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
           inc = d.s + d.c;
         } else {
           double sq4[4] = {0.0, 0.0, 0.0, 0.0};
-          static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], readlane_f64(dy, J), sq4[J % 4]); });
+          static_for<0, M>([&](auto J) { sq4[J % 4] = fma(Bs[r * MS + J], piv[J], sq4[J % 4]); });
           inc = (sq4[0] + sq4[1]) + (sq4[2] + sq4[3]);
           zreg[R] += inc;
         }
@@ -616,7 +620,7 @@ __device__ __forceinline__ int face_forward(const GridDims& g, const GeomPtrs& g
     smax = fmax(smax, __shfl_xor(smax, o));
   }
   const bool settled = dlast <= kSettleTol * smax;
-  if (rank_low) *rank_low = !((pmin > kRankTol * pmax) && (pmax > 0.0));
+  if (rank_low) *rank_low = !((pmin > kRankTol * kRankTol * pmax) && (pmax > 0.0));
   if (!allfinite) return CUTCELL_STATUS_NONFINITE;
   if (!pivots_ok || !cond_ok || !settled) return kStatusRoute;
   return CUTCELL_STATUS_OK;
